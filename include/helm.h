@@ -1,0 +1,155 @@
+/*
+ * helm.h -- C ABI of the MI355X (gfx950) FFT-based fast direct solver for the
+ * separable finite-element Helmholtz problem
+ *
+ *     -Laplace(u) - omega^2 u = f   in [0, L_1] x ... x [0, L_d],  d = 2, 3,
+ *     du/dn - i*omega*u = 0 on absorbing faces, du/dn = 0 on Neumann faces,
+ *
+ * discretised by bilinear (9-point) or trilinear (27-point) elements on a
+ * uniform tensor mesh (Toivanen & Wolfmayr, "A fast Fourier transform based
+ * direct solver for the Helmholtz problem", Section 2, eqs. (A2D), (A3D)).
+ *
+ * The solve is the three-step method of Section 3.1 (periodic auxiliary
+ * problem along x_1, boundary partial solution, corrected periodic solve), in
+ * 3D nested along x_2 as in Section 5: forward DFTs along the periodised axes,
+ * batched complex tridiagonal solves along the last axis, inverse DFTs.
+ *
+ * Conventions shared by every entry point:
+ *   - Arrays are complex128, interleaved (re, im) doubles, C-ordered
+ *     [nrhs][n_1][n_2]([n_3]) with x_1 the slowest axis (the Kronecker
+ *     ordering of eqs. (A2D), (A3D)).
+ *   - Pointers named f, u, r are DEVICE pointers (memory of the current HIP
+ *     device, e.g. torch tensors' data_ptr()); the caller owns them.
+ *   - stream is a hipStream_t or NULL for the default stream.
+ *   - Every function returns a status code (HELM_OK = 0, negative on error);
+ *     no C++ exception crosses this boundary.
+ */
+#ifndef HELM_H
+#define HELM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes. */
+#define HELM_OK            0
+#define HELM_EINVAL       -1  /* bad argument: dimension, grid < 3, nrhs < 1, null pointer */
+#define HELM_ENOMEM       -2  /* device or host allocation failed */
+#define HELM_EDEVICE      -3  /* a HIP runtime call failed */
+#define HELM_ESINGULAR    -4  /* the system is singular (e.g. omega = 0 with no absorbing face) */
+#define HELM_ENOCONV      -5  /* refinement did not reach tol within max_iter (u holds the last iterate) */
+#define HELM_ENONFINITE   -6  /* f (or an intermediate residual) holds NaN or Inf */
+#define HELM_EUNSUPPORTED -7  /* valid problem outside what this build implements */
+
+/* Precision of the bulk transforms and tridiagonal sweeps. */
+#define HELM_PREC_FP64   0  /* complex128 storage and arithmetic throughout */
+#define HELM_PREC_MIXED  1  /* complex64 storage of the transforms and sweep inputs/outputs,
+                               FP64 recurrence arithmetic, FP64 stencil residual and
+                               FP64 solution update (iterative refinement) */
+
+/* Solver options.  helm_default_options fills: precision = HELM_PREC_FP64,
+ * tol = 1e-10, max_iter = 8, check = 1. */
+typedef struct helm_options {
+    int    precision; /* HELM_PREC_FP64 or HELM_PREC_MIXED */
+    double tol;       /* target ||f - A u||_2 / ||f||_2 per right-hand side */
+    int    max_iter;  /* maximum refinement steps after the first solve */
+    int    check;     /* FP64 path: 1 = evaluate the FP64 residual after the solve and
+                         refine while it exceeds tol; 0 = one plain solve, no residual.
+                         The mixed path always checks. */
+} helm_options;
+
+void helm_default_options(helm_options* opt);
+
+/* Opaque plan: owns the 1D spectral data, the device tables and its device
+ * workspace. */
+typedef struct helm_plan helm_plan;
+
+/*
+ * helm_setup -- build a plan for one operator (Sections 3.2, 4.1, 5.1).
+ *   dim    2 or 3
+ *   grid   host array of dim node counts n_j >= 3 (nodes 0..n_j-1)
+ *   h      host array of dim mesh sizes h_j > 0 (the paper uses h_j = 1/(n_j - 1))
+ *   omega  wavenumber (finite)
+ *   abc    face mask: bit 2j = low face of axis j is absorbing, bit 2j+1 = high
+ *          face; clear bits are Neumann faces.  Each periodised axis (x_1, and
+ *          x_2 in 3D) needs the same condition on both of its faces; the last
+ *          axis needs at least one absorbing face (else its tridiagonal
+ *          systems can be exactly singular).
+ *   opt    options or NULL for the defaults
+ *   out    receives the plan
+ * Computes the FP64 1D spectra on the host: closed-form periodic spectra
+ * (eqs. (eigvectorsPer), (eigvaluesPer)) and the absorbing-boundary
+ * generalized eigenpairs K V = M V Lambda^A (eq. (EVP1a), normalised as in
+ * eq. (EVPcondA)), then uploads them to the current HIP device.
+ * Errors: HELM_EINVAL, HELM_ESINGULAR (omega = 0 and no absorbing face),
+ * HELM_EUNSUPPORTED (a periodised axis with mixed face conditions, or a
+ * periodised length this build cannot transform), HELM_ENOMEM, HELM_EDEVICE.
+ */
+int helm_setup(int dim, const int64_t* grid, const double* h, double omega,
+               uint32_t abc, const helm_options* opt, helm_plan** out);
+
+/*
+ * helm_solve -- u = A^{-1} f for nrhs right-hand sides.
+ *   f  device, read only, complex128 [nrhs][grid]
+ *   u  device, written, complex128 [nrhs][grid]; must not overlap f
+ * All kernels run on `stream`.  With checking (mixed precision, or FP64 with
+ * opt.check = 1) the call synchronises `stream` once per refinement step to
+ * read the residual norms; a plain FP64 solve (check = 0) is fully
+ * asynchronous.  The plan's workspace grows on demand for larger nrhs; a plan
+ * must not be used from two streams at once.
+ * Errors: HELM_EINVAL, HELM_ENOMEM, HELM_EDEVICE, HELM_ENOCONV (u holds the
+ * last iterate), HELM_ENONFINITE (f holds NaN/Inf).
+ */
+int helm_solve(helm_plan* p, const void* f, void* u, int nrhs, void* stream);
+
+/* Report of the last helm_solve on this plan. */
+typedef struct helm_report {
+    int    status;            /* status returned by the last solve */
+    int    iterations;        /* refinement steps taken after the first solve */
+    int    precision;         /* HELM_PREC_* used */
+    int    nrhs;
+    double rel_residual_max;  /* max over RHS of ||f - A u|| / ||f|| (FP64), -1 if unchecked */
+    double rel_residual_first;/* same after the first solve, -1 if unchecked */
+} helm_report;
+
+int helm_report_get(const helm_plan* p, helm_report* out);
+
+/*
+ * helm_residual -- r = f - A u in FP64 with the matrix-free 9-/27-point
+ * operator of eqs. (A2D)/(A3D), and per right-hand side
+ * rel_res[k] = ||r_k||_2 / ||f_k||_2.
+ *   u, f  device, complex128 [nrhs][grid]
+ *   r     device complex128 [nrhs][grid], or NULL to compute the norms only
+ *   rel_res host array of nrhs doubles (written after the stream is synchronised)
+ */
+int helm_residual(helm_plan* p, const void* u, const void* f, void* r,
+                  double* rel_res, int nrhs, void* stream);
+
+/* Release the plan and its device memory (synchronises the device first). */
+void helm_destroy(helm_plan* p);
+
+/* Static description of a status code. */
+const char* helm_strerror(int code);
+
+/*
+ * helm_eig1d -- host-only FP64 generalized eigenpairs of the 1D pencil
+ * (K, M) of eqs. (matrixK), (matrixM): K v_l = lambda_l M v_l (eq. (EVP1a)),
+ * normalised v_l^T M v_l = 1 (eq. (EVPcondA), plain transpose).
+ *   n       nodes (>= 3), h mesh size, omega wavenumber
+ *   abc_lo, abc_hi  1 = absorbing face, 0 = Neumann face
+ *   lam     host, 2n doubles: eigenvalues (interleaved complex), sorted by real part
+ *   vb      host, 4n doubles: boundary rows [2][n] complex: vb[0][l] = v_l(0),
+ *           vb[1][l] = v_l(n-1); the common sign of a column is arbitrary
+ * Runs no device code.  Errors: HELM_EINVAL, HELM_ENOCONV (root finder or
+ * refinement failed), HELM_ENOMEM.
+ */
+int helm_eig1d(int64_t n, double h, double omega, int abc_lo, int abc_hi,
+               double* lam, double* vb);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HELM_H */

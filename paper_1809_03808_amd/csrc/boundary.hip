@@ -1,0 +1,157 @@
+// Boundary kernels of Steps 2 and 3.
+//
+// B - A is non-zero only on the two end nodes of the periodised axis (eq.
+// (BminA)); its non-zero block C_bb (eq. (Cbb)) is never formed: with the 2x2
+// differences dK = K^B - K and dM = M^B - M of that axis,
+//   2D:  C = (dK_1 - w^2 dM_1) (x) M_2 + dM_1 (x) K_2,
+//   3D:  C = (dK_1 - w^2 dM_1) (x) M_2 (x) M_3 + dM_1 (x) (K_2 (x) M_3 + M_2 (x) K_3),
+// and on the inner level of 3D (the shifted 2D problems of eqs. (A2D2)-(B2D2aux))
+//   C_2(p) = (dK_2 - p dM_2) (x) M_3 + dM_2 (x) K_3,  p = w^2 - lambda_{1,l}.
+// These kernels sum the per-tile partial reductions of the line solves into
+// the boundary values v_b, w_b (eqs. (2dBs1), (step2-3)) and apply C to them
+// (eqs. (step2-1), (step3term)).
+#include "helm_internal.h"
+#include "ops1d.h"
+
+namespace helm {
+
+namespace {
+
+constexpr int kMidThreads = 256;
+
+__global__ __launch_bounds__(kMidThreads) void sum_partials_kernel(const double2* __restrict__ part,
+                                                                   int64_t ngroups, int ntiles, int nL,
+                                                                   double2* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * kMidThreads + threadIdx.x;
+  const int64_t per = 2 * (int64_t)nL;
+  if (i >= ngroups * per) return;
+  const int64_t g = i / per, r = i - g * per;
+  const double2* p = part + g * ntiles * per + r;
+  double2 s = make_double2(0, 0);
+  for (int t = 0; t < ntiles; ++t) s = cadd(s, p[t * per]);
+  out[i] = s;
+}
+
+// One block per (group, x-tile); LDS holds v over the tile plus a halo of 1.
+__global__ __launch_bounds__(kMidThreads) void inner_mid_kernel(InnerMidArgs a) {
+  __shared__ double2 v[2][kMidThreads + 2];
+  const int ntx = (a.nL + kMidThreads - 1) / kMidThreads;
+  const int64_t g = blockIdx.x / ntx;
+  const int x0 = (int)(blockIdx.x % ntx) * kMidThreads;
+  const int nL = a.nL;
+  const int64_t per = 2 * (int64_t)nL;
+  for (int s = threadIdx.x; s < kMidThreads + 2; s += kMidThreads) {
+    const int x = x0 - 1 + s;
+    for (int k = 0; k < 2; ++k) {
+      double2 acc = make_double2(0, 0);
+      if (x >= 0 && x < nL) {
+        const double2* p = a.part + g * a.ntiles * per + k * nL + x;
+        for (int t = 0; t < a.ntiles; ++t) acc = cadd(acc, p[t * per]);
+        if (a.vb_out) a.vb_out[g * per + k * nL + x] = acc;
+        if (a.vb_in) acc = cadd(acc, a.vb_in[g * per + k * nL + x]);
+      }
+      v[k][s] = acc;
+    }
+  }
+  __syncthreads();
+  const int x = x0 + threadIdx.x;
+  if (x >= nL) return;
+  const int64_t l = g % a.nO;
+  double2 p = make_double2(-a.sC.x, -a.sC.y);
+  if (a.sO) p = csub(p, a.sO[l]);
+  // A = dK - p dM (2x2 complex)
+  double2 A[2][2];
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j)
+      A[i][j] = make_double2(a.d.dK[i][j].x - p.x * a.d.dM[i][j], a.d.dK[i][j].y - p.y * a.d.dM[i][j]);
+  double2 Mv[2], Kv[2];
+  for (int k = 0; k < 2; ++k) {
+    Mv[k] = make_double2(0, 0);
+    Kv[k] = make_double2(0, 0);
+    for (int o = -1; o <= 1; ++o) {
+      const double2 vv = v[k][threadIdx.x + 1 + o];
+      Mv[k] = cadd(Mv[k], cscale(vv, m1d(nL, a.hL, x, o)));
+      Kv[k] = cfma(k1d(nL, a.hL, a.kLo, a.kHi, x, o), vv, Kv[k]);
+    }
+  }
+  for (int k = 0; k < 2; ++k) {
+    double2 r = make_double2(0, 0);
+    for (int kp = 0; kp < 2; ++kp) {
+      r = cfma(A[k][kp], Mv[kp], r);
+      r = cadd(r, cscale(Kv[kp], a.d.dM[k][kp]));
+    }
+    a.out[g * per + k * nL + x] = r;
+  }
+}
+
+// Outer operator on physical planes [nb][2][n2][n3]; one thread per (b, i2, i3).
+__global__ __launch_bounds__(kMidThreads) void outer_mid_kernel(OuterMidArgs a) {
+  const int64_t plane = (int64_t)a.n2 * a.n3;
+  const int64_t idx = (int64_t)blockIdx.x * kMidThreads + threadIdx.x;
+  if (idx >= (int64_t)a.nb * plane) return;
+  const int64_t b = idx / plane;
+  const int64_t rem = idx - b * plane;
+  const int i2 = (int)(rem / a.n3), i3 = (int)(rem % a.n3);
+  double2 MM[2], KS[2];  // (M2 (x) M3) v_k and (K2 (x) M3 + M2 (x) K3) v_k
+  for (int k = 0; k < 2; ++k) {
+    MM[k] = make_double2(0, 0);
+    KS[k] = make_double2(0, 0);
+    const int64_t pb = (b * 2 + k) * plane;
+    for (int o2 = -1; o2 <= 1; ++o2) {
+      const double m2 = m1d(a.n2, a.h2, i2, o2);
+      const double2 kk2 = k1d(a.n2, a.h2, a.k2Lo, a.k2Hi, i2, o2);
+      if (m2 == 0.0) continue;
+      for (int o3 = -1; o3 <= 1; ++o3) {
+        const double m3 = m1d(a.n3, a.h3, i3, o3);
+        if (m3 == 0.0) continue;
+        const double2 kk3 = k1d(a.n3, a.h3, a.k3Lo, a.k3Hi, i3, o3);
+        const int64_t j = pb + (int64_t)(i2 + o2) * a.n3 + (i3 + o3);
+        double2 vv = a.a[j];
+        if (a.c) vv = cadd(vv, a.c[j]);
+        MM[k] = cadd(MM[k], cscale(vv, m2 * m3));
+        // K2(i2,o2) M3(i3,o3) + M2(i2,o2) K3(i3,o3)
+        const double2 coef = make_double2(kk2.x * m3 + m2 * kk3.x, kk2.y * m3 + m2 * kk3.y);
+        KS[k] = cfma(coef, vv, KS[k]);
+      }
+    }
+  }
+  for (int k = 0; k < 2; ++k) {
+    double2 r = make_double2(0, 0);
+    for (int kp = 0; kp < 2; ++kp) {
+      const double2 A = make_double2(a.d1.dK[k][kp].x - a.w2 * a.d1.dM[k][kp], a.d1.dK[k][kp].y);
+      r = cfma(A, MM[kp], r);
+      r = cadd(r, cscale(KS[kp], a.d1.dM[k][kp]));
+    }
+    a.r[(b * 2 + k) * plane + rem] = r;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_sum_partials(const double2* part, int ngroups, int ntiles, int nL, double2* out,
+                               hipStream_t s) {
+  const int64_t n = (int64_t)ngroups * 2 * nL;
+  if (n <= 0) return hipSuccess;
+  const int64_t blocks = (n + kMidThreads - 1) / kMidThreads;
+  hipLaunchKernelGGL(sum_partials_kernel, dim3((unsigned)blocks), dim3(kMidThreads), 0, s, part,
+                     (int64_t)ngroups, ntiles, nL, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_inner_mid(const InnerMidArgs& a, hipStream_t s) {
+  const int ntx = (a.nL + kMidThreads - 1) / kMidThreads;
+  const int64_t blocks = (int64_t)a.nb * a.nO * ntx;
+  if (blocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(inner_mid_kernel, dim3((unsigned)blocks), dim3(kMidThreads), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_outer_mid(const OuterMidArgs& a, hipStream_t s) {
+  const int64_t n = (int64_t)a.nb * a.n2 * a.n3;
+  if (n <= 0) return hipSuccess;
+  const int64_t blocks = (n + kMidThreads - 1) / kMidThreads;
+  hipLaunchKernelGGL(outer_mid_kernel, dim3((unsigned)blocks), dim3(kMidThreads), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace helm

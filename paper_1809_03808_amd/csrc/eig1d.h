@@ -1,0 +1,16 @@
+// Host FP64 eigen-setup of the 1D absorbing-boundary pencil (eig1d.cpp).
+#pragma once
+
+#include <complex>
+#include <vector>
+
+namespace helm {
+
+// All eigenpairs of K v = lambda M v for the 1D matrices of eqs. (matrixK),
+// (matrixM) on n nodes with mesh size h; lo/hi = 1 for an absorbing face.
+// Eigenvectors are normalised v^T M v = 1; v0[l] = v_l(0), v1[l] = v_l(n-1).
+// Returns a HELM_* status.
+int eig1d(int n, double h, double omega, int lo, int hi, std::vector<std::complex<double>>& lam,
+          std::vector<std::complex<double>>& v0, std::vector<std::complex<double>>& v1);
+
+}  // namespace helm

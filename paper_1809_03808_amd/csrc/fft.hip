@@ -1,0 +1,277 @@
+// Batched strided DFT passes for gfx950.
+//
+// The forward eigen-transform of the periodic auxiliary problem is a DFT
+// along a periodised axis with F[l, i] = e^{-2 pi i l i / n} (the eigenvector
+// matrix of the circulant pencil, eq. (eigvectorsPer)), and the final
+// transform is its inverse with the 1/n factor (eq. (step3IFFTz3coeff)).  The
+// periodised axes are never the contiguous one, so each pass works on a tile
+// [L][W] = (transform axis) x (W consecutive contiguous columns): global loads
+// and stores are W*sizeof(complex) contiguous bytes per row, and the L-point
+// transform runs as Stockham radix-2/4/8 stages through LDS.  The first stage
+// reads global memory and the last stage writes it, so a pass touches HBM
+// exactly once each way.  Long axes are split into two passes (four-step:
+// n = n_a n_b, twiddle e^{-2 pi i a c/n} between the passes).
+#include "helm_internal.h"
+
+namespace helm {
+
+namespace {
+
+constexpr int kFftThreads = 256;
+constexpr int kFftLdsBytes = 64 * 1024;
+
+template <typename C> struct RealOf;
+template <> struct RealOf<double2> { using T = double; };
+template <> struct RealOf<float2> { using T = float; };
+
+template <typename C> __device__ inline C load_as(const void* base, int64_t idx, int kind) {
+  if (kind == ST_C128) {
+    const double2 v = reinterpret_cast<const double2*>(base)[idx];
+    C r;
+    r.x = (typename RealOf<C>::T)v.x;
+    r.y = (typename RealOf<C>::T)v.y;
+    return r;
+  }
+  const float2 v = reinterpret_cast<const float2*>(base)[idx];
+  C r;
+  r.x = (typename RealOf<C>::T)v.x;
+  r.y = (typename RealOf<C>::T)v.y;
+  return r;
+}
+
+template <typename C> __device__ inline void store_as(void* base, int64_t idx, int kind, C v, int acc) {
+  if (kind == ST_C128) {
+    double2* p = reinterpret_cast<double2*>(base) + idx;
+    double2 w = make_double2((double)v.x, (double)v.y);
+    if (acc) {
+      const double2 o = *p;
+      w.x += o.x;
+      w.y += o.y;
+    }
+    *p = w;
+  } else {
+    float2* p = reinterpret_cast<float2*>(base) + idx;
+    float2 w = make_float2((float)v.x, (float)v.y);
+    if (acc) {
+      const float2 o = *p;
+      w.x += o.x;
+      w.y += o.y;
+    }
+    *p = w;
+  }
+}
+
+// multiply by (sign * i)
+template <typename C> __device__ inline C mul_si(C a, int sign) {
+  C r;
+  if (sign > 0) { r.x = -a.y; r.y = a.x; }
+  else { r.x = a.y; r.y = -a.x; }
+  return r;
+}
+
+template <int R, typename C> __device__ inline void dft(C* v, int sign);
+
+template <> __device__ inline void dft<2, double2>(double2* v, int) {
+  const double2 a = v[0], b = v[1];
+  v[0] = cadd(a, b);
+  v[1] = csub(a, b);
+}
+template <> __device__ inline void dft<2, float2>(float2* v, int) {
+  const float2 a = v[0], b = v[1];
+  v[0] = cadd(a, b);
+  v[1] = csub(a, b);
+}
+
+template <typename C> __device__ inline void dft4(C& x0, C& x1, C& x2, C& x3, int sign) {
+  const C a = cadd(x0, x2), b = csub(x0, x2), c = cadd(x1, x3), d = mul_si(csub(x1, x3), sign);
+  x0 = cadd(a, c);
+  x1 = cadd(b, d);
+  x2 = csub(a, c);
+  x3 = csub(b, d);
+}
+
+template <> __device__ inline void dft<4, double2>(double2* v, int sign) { dft4(v[0], v[1], v[2], v[3], sign); }
+template <> __device__ inline void dft<4, float2>(float2* v, int sign) { dft4(v[0], v[1], v[2], v[3], sign); }
+
+template <typename C> __device__ inline void dft8(C* v, int sign) {
+  using T = typename RealOf<C>::T;
+  C e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
+  C o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
+  dft4(e0, e1, e2, e3, sign);
+  dft4(o0, o1, o2, o3, sign);
+  const T c = (T)0.70710678118654752440;
+  // w^1 = c(1 + s i), w^2 = s i, w^3 = c(-1 + s i)
+  C t1, t3;
+  {
+    const C si = mul_si(o1, sign);
+    t1.x = c * (o1.x + si.x);
+    t1.y = c * (o1.y + si.y);
+  }
+  const C t2 = mul_si(o2, sign);
+  {
+    const C si = mul_si(o3, sign);
+    t3.x = c * (si.x - o3.x);
+    t3.y = c * (si.y - o3.y);
+  }
+  v[0] = cadd(e0, o0);
+  v[4] = csub(e0, o0);
+  v[1] = cadd(e1, t1);
+  v[5] = csub(e1, t1);
+  v[2] = cadd(e2, t2);
+  v[6] = csub(e2, t2);
+  v[3] = cadd(e3, t3);
+  v[7] = csub(e3, t3);
+}
+template <> __device__ inline void dft<8, double2>(double2* v, int sign) { dft8(v, sign); }
+template <> __device__ inline void dft<8, float2>(float2* v, int sign) { dft8(v, sign); }
+
+struct PassDev {
+  int L, W, nst, sign, acc, in_kind, out_kind;
+  int radix[8];
+  int64_t I, od, in_so, in_sj, out_so1, out_so2, out_sk, tw4_S;
+  int tw4_n;
+  int64_t ntile;  // tiles along I
+  double scale_c;
+  const void* tw;
+  const void* tw4;
+  const double* scale;
+};
+
+// One Stockham stage: X (L points per column) -> Y.  Each thread owns the
+// butterflies t = tid + q*NT, t -> (j = t / W, w = t % W).  All reads of the
+// stage happen before the barrier, all writes after it, so X and Y may be
+// the same LDS buffer.
+template <int R, int VMAX, typename C>
+__device__ inline void run_stage(const PassDev& p, int Ns, bool first, bool last, C* sm,
+                                 const void* in, void* out, int64_t o, int64_t i0) {
+  constexpr int NB = VMAX / R;  // butterflies per thread (upper bound)
+  const int L = p.L, W = p.W;
+  const int LR = L / R;
+  const int nbf = LR * W;
+  const int tid = threadIdx.x;
+  const C* tw = reinterpret_cast<const C*>(p.tw);
+  C v[NB][R];
+#pragma unroll
+  for (int q = 0; q < NB; ++q) {
+    const int t = tid + q * kFftThreads;
+    if (t < nbf) {
+      const int w = t % W, j = t / W;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int row = j + r * LR;
+        if (first) {
+          const int64_t col = i0 + w;
+          C x;
+          if (col < p.I) x = load_as<C>(in, o * p.in_so + (int64_t)row * p.in_sj + col, p.in_kind);
+          else { x.x = 0; x.y = 0; }
+          v[q][r] = x;
+        } else {
+          v[q][r] = sm[row * W + w];
+        }
+      }
+    }
+  }
+  if (!first) __syncthreads();
+#pragma unroll
+  for (int q = 0; q < NB; ++q) {
+    const int t = tid + q * kFftThreads;
+    if (t < nbf) {
+      const int w = t % W, j = t / W;
+      const int k = j % Ns;
+      if (Ns > 1) {
+        const int step = L / (Ns * R);
+#pragma unroll
+        for (int r = 1; r < R; ++r) v[q][r] = cmul(v[q][r], tw[r * k * step]);
+      }
+      dft<R, C>(v[q], p.sign);
+      const int base = (j / Ns) * Ns * R + k;
+      if (!last) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) sm[(base + r * Ns) * W + w] = v[q][r];
+      } else {
+        const int64_t col = i0 + w;
+        if (col < p.I) {
+          const int64_t oq = o / p.od, orr = o % p.od;
+#pragma unroll
+          for (int r = 0; r < R; ++r) {
+            const int64_t kk = base + r * Ns;  // output frequency of this pass
+            C y = v[q][r];
+            if (p.tw4) {
+              const C* t4 = reinterpret_cast<const C*>(p.tw4);
+              y = cmul(y, t4[(kk * (col / p.tw4_S)) % p.tw4_n]);
+            }
+            double s = p.scale_c;
+            if (p.scale) s *= p.scale[orr + p.od * kk];
+            y.x = (typename RealOf<C>::T)(y.x * s);
+            y.y = (typename RealOf<C>::T)(y.y * s);
+            store_as<C>(out, oq * p.out_so1 + orr * p.out_so2 + kk * p.out_sk + col, p.out_kind, y,
+                        p.acc);
+          }
+        }
+      }
+    }
+  }
+  if (!last) __syncthreads();
+}
+
+template <typename C>
+__global__ __launch_bounds__(kFftThreads) void fft_pass_kernel(PassDev p, const void* in, void* out) {
+  extern __shared__ unsigned char smem_raw[];
+  C* sm = reinterpret_cast<C*>(smem_raw);
+  constexpr int VMAX = kFftLdsBytes / (int)sizeof(C) / kFftThreads;
+  const int64_t blk = blockIdx.x;
+  const int64_t o = blk / p.ntile;
+  const int64_t i0 = (blk % p.ntile) * p.W;
+  int Ns = 1;
+  for (int st = 0; st < p.nst; ++st) {
+    const bool first = st == 0, last = st == p.nst - 1;
+    switch (p.radix[st]) {
+      case 8: run_stage<8, VMAX, C>(p, Ns, first, last, sm, in, out, o, i0); break;
+      case 4: run_stage<4, VMAX, C>(p, Ns, first, last, sm, in, out, o, i0); break;
+      default: run_stage<2, VMAX, C>(p, Ns, first, last, sm, in, out, o, i0); break;
+    }
+    Ns *= p.radix[st];
+  }
+}
+
+}  // namespace
+
+hipError_t launch_fft_pass(const FftPass& f, bool fp32, const void* in, void* out, hipStream_t s) {
+  PassDev p;
+  p.L = f.L;
+  p.W = f.W;
+  p.nst = f.nst;
+  for (int i = 0; i < 8; ++i) p.radix[i] = f.radix[i];
+  p.I = f.I;
+  p.od = f.od;
+  p.in_so = f.in_so;
+  p.in_sj = f.in_sj;
+  p.out_so1 = f.out_so1;
+  p.out_so2 = f.out_so2;
+  p.out_sk = f.out_sk;
+  p.tw4_S = f.tw4_S;
+  p.tw4_n = f.tw4_n;
+  p.acc = f.accumulate;
+  p.in_kind = f.in_kind;
+  p.out_kind = f.out_kind;
+  p.scale_c = f.scale_c;
+  p.tw = f.tw;
+  p.tw4 = f.tw4;
+  p.scale = f.scale;
+  p.sign = f.sign;
+  p.ntile = (f.I + f.W - 1) / f.W;
+  const size_t esz = fp32 ? sizeof(float2) : sizeof(double2);
+  const size_t lds = (size_t)f.L * f.W * esz;
+  if (f.L < 2 || f.W < 1 || lds > (size_t)kFftLdsBytes || (int64_t)f.L * f.W > (int64_t)kFftLdsBytes / (int64_t)esz)
+    return hipErrorInvalidValue;
+  const int64_t blocks = f.O * p.ntile;
+  if (blocks <= 0) return hipSuccess;
+  if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+  if (fp32)
+    hipLaunchKernelGGL(fft_pass_kernel<float2>, dim3((unsigned)blocks), dim3(kFftThreads), lds, s, p, in, out);
+  else
+    hipLaunchKernelGGL(fft_pass_kernel<double2>, dim3((unsigned)blocks), dim3(kFftThreads), lds, s, p, in, out);
+  return hipGetLastError();
+}
+
+}  // namespace helm

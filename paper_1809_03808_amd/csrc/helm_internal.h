@@ -1,0 +1,200 @@
+// Internal declarations of the HIP fast Helmholtz solver (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <complex>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/helm.h"
+#include "eig1d.h"
+
+namespace helm {
+
+using cd = std::complex<double>;
+
+// ---------------------------------------------------------------------------
+// complex helpers on HIP vector types (x = re, y = im)
+// ---------------------------------------------------------------------------
+__host__ __device__ inline double2 mk(double r, double i) { return make_double2(r, i); }
+__host__ __device__ inline float2 mk(float r, float i) { return make_float2(r, i); }
+template <typename C> __device__ inline C cadd(C a, C b) { a.x += b.x; a.y += b.y; return a; }
+template <typename C> __device__ inline C csub(C a, C b) { a.x -= b.x; a.y -= b.y; return a; }
+template <typename C> __device__ inline C cmul(C a, C b) {
+  C r;
+  r.x = a.x * b.x - a.y * b.y;
+  r.y = a.x * b.y + a.y * b.x;
+  return r;
+}
+// a + b*c
+template <typename C> __device__ inline C cfma(C b, C c, C a) {
+  a.x += b.x * c.x - b.y * c.y;
+  a.y += b.x * c.y + b.y * c.x;
+  return a;
+}
+template <typename C, typename S> __device__ inline C cscale(C a, S s) { a.x *= s; a.y *= s; return a; }
+__device__ inline double2 crcp(double2 a) {
+  const double d = 1.0 / (a.x * a.x + a.y * a.y);
+  return make_double2(a.x * d, -a.y * d);
+}
+__device__ inline double2 to_d2(double2 a) { return a; }
+__device__ inline double2 to_d2(float2 a) { return make_double2((double)a.x, (double)a.y); }
+template <typename C> __device__ inline C from_d2(double2 a);
+template <> __device__ inline double2 from_d2<double2>(double2 a) { return a; }
+template <> __device__ inline float2 from_d2<float2>(double2 a) { return make_float2((float)a.x, (float)a.y); }
+
+inline double2 hd2(cd z) { return make_double2(z.real(), z.imag()); }
+
+
+// ---------------------------------------------------------------------------
+// Batched strided DFT pass (fft.hip)
+// Data viewed as [O][L (stride in_sj)][I (contiguous)]; a pass computes a
+// length-L DFT for every (o, i) and writes output k of (o, i) to
+//   (o / od) * out_so1 + (o % od) * out_so2 + k * out_sk + i,
+// optionally multiplied by a four-step twiddle tw4[(k * (i / tw4_S)) % tw4_n]
+// and a per-mode real scale scale[(o % od) + od * k] * scale_c.
+// ---------------------------------------------------------------------------
+enum StorageKind { ST_C128 = 0, ST_C64 = 1 };
+
+struct FftPass {
+  int L = 0;
+  int nst = 0;
+  int radix[8] = {0};
+  int64_t I = 0, O = 0;
+  int64_t od = 1;
+  int64_t in_so = 0, in_sj = 0;
+  int64_t out_so1 = 0, out_so2 = 0, out_sk = 0;
+  int64_t tw4_S = 0;  // 0: no four-step twiddle
+  int tw4_n = 0;
+  int W = 0;          // inner columns per workgroup
+  int in_kind = ST_C128, out_kind = ST_C128;
+  int accumulate = 0;
+  int sign = -1;      // -1 forward (e^{-2 pi i ...}), +1 inverse
+  double scale_c = 1.0;
+  // device tables (double or float per compute precision), owned by the plan
+  const void* tw = nullptr;    // L roots e^{sign 2 pi i t / L}
+  const void* tw4 = nullptr;   // tw4_n roots
+  const double* scale = nullptr;
+};
+
+// Launch one pass.  `fp32` selects float arithmetic (tables in float).
+hipError_t launch_fft_pass(const FftPass& p, bool fp32, const void* in, void* out,
+                           hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// Batched tridiagonal line solves (lines.hip)
+// Line (b, l, m), b < nb, l < nO, m < nI, has the matrix
+//   T = sigma M_L + K_L,  sigma = sO[l] + sI[m] + sC,
+// with M_L = (hL/6) tridiag(1,4,1) (corners 2) and K_L = (1/hL) tridiag(-1,2,-1)
+// with corner entries kLo/hL, kHi/hL, along the contiguous axis of length nL.
+// Right-hand side:
+//   in[b][l][m][:] (if in)  + sum_k alpha_k[l] PO[b][k][m][:]  (if PO)
+//                           + sum_k beta_k[m]  PI[b][l][k][:]  (if PI)
+// Output: store the solution to out[b][l][m][:] and/or reduce
+//   red == 1: part[((b nO + l) ntiles + t)][k][:] = sum_{m in tile t} rho_k[m] y
+//   red == 2: part[((b nI + m) ntiles + t)][k][:] = sum_{l in tile t} rho_k[l] y
+// ---------------------------------------------------------------------------
+struct LineArgs {
+  int nb = 1, nO = 1, nI = 1, nL = 0;
+  const double2* sO = nullptr;
+  const double2* sI = nullptr;
+  double2 sC = {0, 0};
+  double hL = 0;
+  double2 kLo = {1, 0}, kHi = {1, 0};
+  const void* in = nullptr;
+  int in_kind = ST_C128;
+  const double2* alpha0 = nullptr;
+  const double2* alpha1 = nullptr;
+  const double2* PO = nullptr;
+  const double2* beta0 = nullptr;
+  const double2* beta1 = nullptr;
+  const double2* PI = nullptr;
+  void* out = nullptr;
+  int out_kind = ST_C128;
+  int red = 0;
+  const double2* rho0 = nullptr;
+  const double2* rho1 = nullptr;
+  double2* part = nullptr;
+  int tile = 0;    // lines per workgroup tile
+  int ntiles = 0;  // tiles along the reduced (or flattened) index
+};
+
+hipError_t launch_lines(LineArgs a, hipStream_t s);
+// Number of partial planes per reduction group for a given tile request.
+int lines_tile(const LineArgs& a, int reduce_extent, int target_blocks);
+
+// ---------------------------------------------------------------------------
+// Boundary kernels (boundary.hip)
+// ---------------------------------------------------------------------------
+// 2x2 boundary difference of a periodised axis (B - A restricted to its two
+// end nodes): dK = (1/h)[[1 + i w h a_lo, -1], [-1, 1 + i w h a_hi]],
+// dM = (h/6)[[2, 1], [1, 2]].
+struct BDiff {
+  double2 dK[2][2];
+  double dM[2][2];
+};
+
+// Inner boundary operator for every (b, l): with v = sum over tiles of
+// part[(b nO + l) ntiles + t][k][:] (+ vb_in[b][l][k][:] if add_vb),
+//   out[b][l][k][:] = sum_k' (dK - p_l dM)[k][k'] M_L v_k' + dM[k][k'] K_L v_k',
+//   p_l = -(sO[l] + sC)  (sO may be null -> p = -sC),
+// and, if vb_out, vb_out[b][l][k][:] = v (the reduced boundary values).
+struct InnerMidArgs {
+  int nb, nO, nL, ntiles;
+  const double2* part;
+  const double2* vb_in;  // nullable
+  double2* vb_out;       // nullable
+  double2* out;
+  const double2* sO;
+  double2 sC;
+  BDiff d;
+  double hL;
+  double2 kLo, kHi;
+};
+hipError_t launch_inner_mid(const InnerMidArgs& a, hipStream_t s);
+
+// Sum partial planes: out[g][k][:] = sum_t part[g ntiles + t][k][:], g < ngroups.
+hipError_t launch_sum_partials(const double2* part, int ngroups, int ntiles, int nL,
+                               double2* out, hipStream_t s);
+
+// Outer boundary operator on physical (x2, x3) planes (3D):
+//   r[b][k] = sum_k' (dK1 - w^2 dM1)[k][k'] (M2 (x) M3) v_k' + dM1[k][k'] (K2 (x) M3 + M2 (x) K3) v_k'
+// with v = a[b] (+ c[b] if c), planes [nb][2][n2][n3].
+struct OuterMidArgs {
+  int nb, n2, n3;
+  const double2* a;
+  const double2* c;  // nullable
+  double2* r;
+  BDiff d1;
+  double w2;
+  double h2, h3;
+  double2 k2Lo, k2Hi, k3Lo, k3Hi;
+};
+hipError_t launch_outer_mid(const OuterMidArgs& a, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// Stencil residual and norms (stencil.hip)
+// ---------------------------------------------------------------------------
+struct AxisOp {
+  int n;
+  double h;
+  double2 kLo, kHi;  // K corner entries times h
+};
+struct ResidArgs {
+  int dim, nb;
+  AxisOp ax[3];
+  double w2;
+  const double2* u;
+  const double2* f;
+  void* r;        // nullable
+  int r_kind;     // ST_C128 / ST_C64
+  double* norms;  // device [nb][2]: sum |r|^2, sum |f|^2 (accumulated by the finishing kernel)
+  double* scratch;
+  int64_t scratch_len;
+};
+hipError_t launch_residual(const ResidArgs& a, hipStream_t s);
+int64_t residual_scratch_len(int dim, const int64_t* grid, int nb);
+
+}  // namespace helm

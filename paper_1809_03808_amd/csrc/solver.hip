@@ -1,0 +1,833 @@
+// Plan setup, pipeline orchestration and the C ABI (include/helm.h).
+//
+// 2D (Section 4.2), with x_1 periodised and lines along x_2:
+//   f^   = F_1 f / mu_1                                      (eq. (step1FFTfcoeff), forward DFT)
+//   Step 1: z1_l = (T^B_l)^{-1} f^_l, v_b = boundary rows of F_1^{-1} z1     (eqs. (2dLUBs1), (2dBs1))
+//   Step 2: r = C v_b, z2_l = (T^A_l)^{-1} (V_1^b)^T r, w_b = V_1^b z2       (eqs. (step2-1)-(step2-3))
+//   Step 3: q = C (v_b + w_b), z3_l = (T^B_l)^{-1} (f^_l + h^_l)             (eqs. (step3term), (2dLUBs3))
+//           u = F_1^{-1} z3                                                  (eq. (step3IFFTz3coeff))
+// 3D (Section 5.2): the same three steps along x_1, each block solve being the
+// 2D method along x_2 on the shifted problems of eqs. (A2D2)-(B2D2aux); by
+// linearity the x_2 transform of every right-hand side is taken once (the
+// whole array for f^, two planes for the boundary terms), and the outer
+// boundary reductions act on the inner solutions in x_2-mode space before a
+// two-plane inverse transform.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <memory>
+
+#include "helm_internal.h"
+
+namespace helm {
+
+namespace {
+
+bool is_pow2(int64_t n) { return n >= 2 && (n & (n - 1)) == 0; }
+
+struct DevMem {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevMem() = default;
+  DevMem(const DevMem&) = delete;
+  DevMem& operator=(const DevMem&) = delete;
+  ~DevMem() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  hipError_t ensure(size_t b) {
+    if (b <= bytes && p) return hipSuccess;
+    release();
+    if (b == 0) return hipSuccess;
+    hipError_t e = hipMalloc(&p, b);
+    if (e != hipSuccess) {
+      p = nullptr;
+      return e;
+    }
+    bytes = b;
+    return hipSuccess;
+  }
+  template <typename T> T* as() const { return reinterpret_cast<T*>(p); }
+};
+
+struct Roots {  // e^{sign 2 pi i t / L}, t < L, in double and float
+  DevMem d, f;
+};
+
+// Periodised axis: closed-form periodic spectra (eqs. (eigvectorsPer),
+// (eigvaluesPer)) and the absorbing-boundary eigenpairs (eq. (EVP1a)).
+struct PAxis {
+  int n = 0;
+  double h = 0;
+  int lo = 0, hi = 0;
+  std::vector<cd> lamA, va0, va1;
+  DevMem tab;  // all per-mode tables below, one allocation
+  double2 *sigB = nullptr, *sigA = nullptr, *genB0 = nullptr, *genB1 = nullptr, *redB0 = nullptr,
+          *redB1 = nullptr, *va0d = nullptr, *va1d = nullptr;
+  double* invmu = nullptr;
+  BDiff bd;
+  int na = 0, nbp = 0;  // FFT split n = na * nbp (nbp = first pass length); na = 1 -> one pass
+};
+
+}  // namespace
+
+}  // namespace helm
+
+struct helm_plan {
+  int dim = 0;
+  int64_t grid[3] = {0, 0, 0};
+  double h[3] = {0, 0, 0};
+  double omega = 0;
+  uint32_t abc = 0;
+  helm_options opt{};
+  int device = 0;
+  helm::PAxis ax[2];
+  int nper = 0;  // periodised axes: 1 (2D) or 2 (3D)
+  // last (line) axis
+  int nL = 0;
+  double hL = 0;
+  double2 kLo{1, 0}, kHi{1, 0};
+  std::map<int, helm::Roots> roots_fwd, roots_inv;
+  // workspace
+  int cap_rhs = 0;
+  int cap_prec = -1;
+  helm::DevMem W0, W1, W2, R, part, VB, PIb, P0, P1, P2, P3, scratch, norms;
+  std::vector<double> h_norms;
+  helm_report rep{};
+};
+
+namespace helm {
+
+namespace {
+
+hipError_t upload(void* dst, const void* src, size_t bytes) {
+  return hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice);
+}
+
+int map_err(hipError_t e) {
+  if (e == hipSuccess) return HELM_OK;
+  if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) return HELM_ENOMEM;
+  return HELM_EDEVICE;
+}
+
+#define HCHK(expr)                      \
+  do {                                  \
+    hipError_t _e = (expr);             \
+    if (_e != hipSuccess) return map_err(_e); \
+  } while (0)
+
+Roots* get_roots(helm_plan* p, int L, int sign) {
+  auto& mp = sign < 0 ? p->roots_fwd : p->roots_inv;
+  auto it = mp.find(L);
+  if (it != mp.end()) return &it->second;
+  Roots& r = mp[L];
+  std::vector<double2> hd(L);
+  std::vector<float2> hf(L);
+  for (int t = 0; t < L; ++t) {
+    // angle 2 pi t / L reduced to the first octant symmetry-free form
+    const double th = 2.0 * M_PI * (double)t / (double)L;
+    const double c = std::cos(th), s = sign * std::sin(th);
+    hd[t] = make_double2(c, s);
+    hf[t] = make_float2((float)c, (float)s);
+  }
+  if (r.d.ensure(L * sizeof(double2)) != hipSuccess || r.f.ensure(L * sizeof(float2)) != hipSuccess) return nullptr;
+  if (upload(r.d.p, hd.data(), L * sizeof(double2)) != hipSuccess) return nullptr;
+  if (upload(r.f.p, hf.data(), L * sizeof(float2)) != hipSuccess) return nullptr;
+  return &r;
+}
+
+void radix_plan(int L, FftPass& f) {
+  int p = 0;
+  while ((1 << p) < L) ++p;
+  f.nst = 0;
+  const int rem = p % 3;
+  if (rem == 1) f.radix[f.nst++] = 2;
+  if (rem == 2) f.radix[f.nst++] = 4;
+  for (int i = 0; i < p / 3; ++i) f.radix[f.nst++] = 8;
+}
+
+int pick_W(int L, int64_t I, bool fp32) {
+  const int esz = fp32 ? 8 : 16;
+  int W = 1;
+  while (W < 64 && (int64_t)(2 * W) * L * esz <= 64 * 1024) W *= 2;
+  while (W > 1 && W / 2 >= I) W /= 2;
+  return W;
+}
+
+// DFT along a periodised axis of data [O][n][S] (S contiguous).
+// Forward: sign -1 and per-mode scale 1/mu (if scale), inverse: sign +1, 1/n.
+int run_fft(helm_plan* p, const PAxis& a, int sign, bool fp32, const void* in, int in_kind, void* out,
+            int out_kind, int64_t O, int64_t S, const double* scale, double scale_c, int accumulate,
+            void* tmp, int tmp_kind, hipStream_t st) {
+  const int n = a.n;
+  if (a.na <= 1) {
+    Roots* r = get_roots(p, n, sign);
+    if (!r) return HELM_ENOMEM;
+    FftPass f;
+    f.L = n;
+    radix_plan(n, f);
+    f.I = S;
+    f.O = O;
+    f.od = 1;
+    f.in_so = (int64_t)n * S;
+    f.in_sj = S;
+    f.out_so1 = (int64_t)n * S;
+    f.out_so2 = 0;
+    f.out_sk = S;
+    f.W = pick_W(n, S, fp32);
+    f.in_kind = in_kind;
+    f.out_kind = out_kind;
+    f.accumulate = accumulate;
+    f.sign = sign;
+    f.scale = scale;
+    f.scale_c = scale_c;
+    f.tw = fp32 ? r->f.p : r->d.p;
+    HCHK(launch_fft_pass(f, fp32, in, out, st));
+    return HELM_OK;
+  }
+  // four-step: n = na * nb, x = a + na b, k = c + nb d
+  const int na = a.na, nb = a.nbp;
+  Roots* r1 = get_roots(p, nb, sign);
+  Roots* r2 = get_roots(p, na, sign);
+  Roots* rn = get_roots(p, n, sign);
+  if (!r1 || !r2 || !rn) return HELM_ENOMEM;
+  FftPass f1;
+  f1.L = nb;
+  radix_plan(nb, f1);
+  f1.I = (int64_t)na * S;
+  f1.O = O;
+  f1.od = 1;
+  f1.in_so = (int64_t)n * S;
+  f1.in_sj = (int64_t)na * S;
+  f1.out_so1 = (int64_t)n * S;
+  f1.out_sk = (int64_t)na * S;
+  f1.tw4_S = S;
+  f1.tw4_n = n;
+  f1.W = pick_W(nb, f1.I, fp32);
+  f1.in_kind = in_kind;
+  f1.out_kind = tmp_kind;
+  f1.sign = sign;
+  f1.tw = fp32 ? r1->f.p : r1->d.p;
+  f1.tw4 = fp32 ? rn->f.p : rn->d.p;
+  HCHK(launch_fft_pass(f1, fp32, in, tmp, st));
+  FftPass f2;
+  f2.L = na;
+  radix_plan(na, f2);
+  f2.I = S;
+  f2.O = O * nb;
+  f2.od = nb;
+  f2.in_so = (int64_t)na * S;
+  f2.in_sj = S;
+  f2.out_so1 = (int64_t)n * S;
+  f2.out_so2 = S;
+  f2.out_sk = (int64_t)nb * S;
+  f2.W = pick_W(na, S, fp32);
+  f2.in_kind = tmp_kind;
+  f2.out_kind = out_kind;
+  f2.accumulate = accumulate;
+  f2.sign = sign;
+  f2.scale = scale;
+  f2.scale_c = scale_c;
+  f2.tw = fp32 ? r2->f.p : r2->d.p;
+  HCHK(launch_fft_pass(f2, fp32, tmp, out, st));
+  return HELM_OK;
+}
+
+// Lines per tile: at least 16 lines feed each partial sum (partials stay
+// below 1/8 of an N-sized array) and enough tiles to fill the chip.
+void tiles_for(int red, int nb, int nO, int nI, int nL, int* tile, int* ntiles) {
+  int P = 1;
+  while (P * 8 < nL) P <<= 1;
+  const int NT = P > 256 ? P : 256;
+  const int LPB = NT / P;
+  const int64_t extent = red == 1 ? nI : (red == 2 ? nO : (int64_t)nb * nO * nI);
+  const int64_t groups = red == 1 ? (int64_t)nb * nO : (red == 2 ? (int64_t)nb * nI : 1);
+  int64_t t = red ? 16 : LPB;
+  const int64_t lines = extent * groups;
+  const int64_t target = 4096;
+  if (lines / t > target) t = (lines + target - 1) / target;
+  if (red && t > extent) t = extent;
+  t = (t + LPB - 1) / LPB * LPB;
+  *tile = (int)t;
+  *ntiles = (int)((extent + t - 1) / t);
+}
+
+size_t part_elems(int red, int nb, int nO, int nI, int nL) {
+  int tile, nt;
+  tiles_for(red, nb, nO, nI, nL, &tile, &nt);
+  const int64_t groups = red == 1 ? (int64_t)nb * nO : (int64_t)nb * nI;
+  return (size_t)groups * nt * 2 * nL;
+}
+
+struct Level {  // geometry of one inner 2D solve, batched over (b, l)
+  int nb, nO, nI, nL;
+  const PAxis* inner;
+  double w2;
+};
+
+// One inner three-step solve (the 2D method of Section 4.2 applied to every
+// outer mode l with sigma shifted by sO[l]): S1 with reduction over m, the
+// boundary operator, S2, the boundary operator, S3 (store or reduce over l).
+struct InnerIO {
+  const double2* sO = nullptr;
+  const void* in = nullptr;
+  int in_kind = ST_C128;
+  const double2* PO = nullptr;
+  const double2* alpha0 = nullptr;
+  const double2* alpha1 = nullptr;
+  void* out = nullptr;
+  int out_kind = ST_C128;
+  const double2* rhoL0 = nullptr;
+  const double2* rhoL1 = nullptr;
+};
+
+int inner_solve(helm_plan* p, const Level& lv, const InnerIO& io, hipStream_t st) {
+  const PAxis& I = *lv.inner;
+  const double2 sC = make_double2(-lv.w2, 0.0);
+  LineArgs base;
+  base.nb = lv.nb;
+  base.nO = lv.nO;
+  base.nI = lv.nI;
+  base.nL = lv.nL;
+  base.sO = io.sO;
+  base.sC = sC;
+  base.hL = p->hL;
+  base.kLo = p->kLo;
+  base.kHi = p->kHi;
+  double2* part = p->part.as<double2>();
+  int tile, nt;
+  tiles_for(1, lv.nb, lv.nO, lv.nI, lv.nL, &tile, &nt);
+
+  // S1: (T^B)^{-1} of the right-hand side, reduced to the two boundary rows.
+  LineArgs s1 = base;
+  s1.sI = I.sigB;
+  s1.in = io.in;
+  s1.in_kind = io.in_kind;
+  s1.PO = io.PO;
+  s1.alpha0 = io.alpha0;
+  s1.alpha1 = io.alpha1;
+  s1.red = 1;
+  s1.rho0 = I.redB0;
+  s1.rho1 = I.redB1;
+  s1.part = part;
+  s1.tile = tile;
+  s1.ntiles = nt;
+  HCHK(launch_lines(s1, st));
+
+  InnerMidArgs m;
+  m.nb = lv.nb;
+  m.nO = lv.nO;
+  m.nL = lv.nL;
+  m.ntiles = nt;
+  m.part = part;
+  m.vb_in = nullptr;
+  m.vb_out = p->VB.as<double2>();
+  m.out = p->PIb.as<double2>();
+  m.sO = io.sO;
+  m.sC = sC;
+  m.d = I.bd;
+  m.hL = p->hL;
+  m.kLo = p->kLo;
+  m.kHi = p->kHi;
+  HCHK(launch_inner_mid(m, st));
+
+  // S2: partial solution with the absorbing-boundary eigenvectors.
+  LineArgs s2 = base;
+  s2.sI = I.sigA;
+  s2.PI = p->PIb.as<double2>();
+  s2.beta0 = I.va0d;
+  s2.beta1 = I.va1d;
+  s2.red = 1;
+  s2.rho0 = I.va0d;
+  s2.rho1 = I.va1d;
+  s2.part = part;
+  s2.tile = tile;
+  s2.ntiles = nt;
+  HCHK(launch_lines(s2, st));
+
+  m.vb_in = p->VB.as<double2>();
+  m.vb_out = nullptr;
+  HCHK(launch_inner_mid(m, st));
+
+  // S3: corrected periodic solve.
+  LineArgs s3 = base;
+  s3.sI = I.sigB;
+  s3.in = io.in;
+  s3.in_kind = io.in_kind;
+  s3.PO = io.PO;
+  s3.alpha0 = io.alpha0;
+  s3.alpha1 = io.alpha1;
+  s3.PI = p->PIb.as<double2>();
+  s3.beta0 = I.genB0;
+  s3.beta1 = I.genB1;
+  if (io.rhoL0) {
+    int tl, ntl;
+    tiles_for(2, lv.nb, lv.nO, lv.nI, lv.nL, &tl, &ntl);
+    s3.red = 2;
+    s3.rho0 = io.rhoL0;
+    s3.rho1 = io.rhoL1;
+    s3.part = part;
+    s3.tile = tl;
+    s3.ntiles = ntl;
+  } else {
+    int tl, ntl;
+    tiles_for(0, lv.nb, lv.nO, lv.nI, lv.nL, &tl, &ntl);
+    s3.out = io.out;
+    s3.out_kind = io.out_kind;
+    s3.tile = tl;
+    s3.ntiles = ntl;
+  }
+  HCHK(launch_lines(s3, st));
+  return HELM_OK;
+}
+
+// Sum reduce-over-l partials [b][m][t][k][x] into planes [b][k][m][x].
+__global__ void sum_to_planes_kernel(const double2* __restrict__ part, int nb, int nI, int nL, int ntiles,
+                                     double2* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t total = (int64_t)nb * 2 * nI * nL;
+  if (i >= total) return;
+  const int64_t x = i % nL;
+  const int64_t m = (i / nL) % nI;
+  const int64_t k = (i / ((int64_t)nL * nI)) % 2;
+  const int64_t b = i / ((int64_t)nL * nI * 2);
+  const double2* pp = part + ((b * nI + m) * ntiles) * 2 * nL + k * nL + x;
+  double2 s = make_double2(0, 0);
+  for (int t = 0; t < ntiles; ++t) s = cadd(s, pp[(int64_t)t * 2 * nL]);
+  out[i] = s;
+}
+
+int sum_to_planes(helm_plan* p, const Level& lv, double2* out, hipStream_t st) {
+  int tl, ntl;
+  tiles_for(2, lv.nb, lv.nO, lv.nI, lv.nL, &tl, &ntl);
+  const int64_t total = (int64_t)lv.nb * 2 * lv.nI * lv.nL;
+  hipLaunchKernelGGL(sum_to_planes_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st,
+                     p->part.as<double2>(), lv.nb, lv.nI, lv.nL, ntl, out);
+  HCHK(hipGetLastError());
+  return HELM_OK;
+}
+
+// Full solve of one precision pass: u (+)= A^{-1} x.
+int solve_once(helm_plan* p, const void* x, int x_kind, double2* u, int accumulate, int nb, bool fp32,
+               hipStream_t st) {
+  const int T = fp32 ? ST_C64 : ST_C128;
+  const double w2 = p->omega * p->omega;
+  void* W0 = p->W0.p;
+  void* W1 = p->W1.p;
+  if (p->dim == 2) {
+    const PAxis& A1 = p->ax[0];
+    const int n1 = A1.n, n2 = p->nL;
+    int rc = run_fft(p, A1, -1, fp32, x, x_kind, W0, T, nb, n2, A1.invmu, 1.0, 0, W1, T, st);
+    if (rc) return rc;
+    Level lv{nb, 1, n1, n2, &A1, w2};
+    InnerIO io;
+    io.in = W0;
+    io.in_kind = T;
+    io.out = W0;
+    io.out_kind = T;
+    rc = inner_solve(p, lv, io, st);
+    if (rc) return rc;
+    return run_fft(p, A1, +1, fp32, W0, T, u, ST_C128, nb, n2, nullptr, 1.0 / n1, accumulate, W1, T, st);
+  }
+  // 3D
+  const PAxis& A1 = p->ax[0];
+  const PAxis& A2 = p->ax[1];
+  const int n1 = A1.n, n2 = A2.n, n3 = p->nL;
+  const int64_t plane = (int64_t)n2 * n3;
+  void* W2 = p->W2.p ? p->W2.p : W1;
+  int rc = run_fft(p, A1, -1, fp32, x, x_kind, W1, T, nb, plane, A1.invmu, 1.0, 0, W2, T, st);
+  if (rc) return rc;
+  rc = run_fft(p, A2, -1, fp32, W1, T, W0, T, (int64_t)nb * n1, n3, A2.invmu, 1.0, 0, W2 == W1 ? W0 : W2, T, st);
+  if (rc) return rc;
+  Level lv{nb, n1, n2, n3, &A2, w2};
+  double2* Vh = p->P0.as<double2>();  // [nb][2][n2][n3] scratch planes
+  double2* Vp = p->P1.as<double2>();
+  double2* Wp = p->P2.as<double2>();
+  double2* Rh = p->P3.as<double2>();
+  const double2* d_null = nullptr;
+  (void)d_null;
+  // Outer step 1: v_b.
+  {
+    InnerIO io;
+    io.sO = A1.sigB;
+    io.in = W0;
+    io.in_kind = T;
+    io.rhoL0 = A1.redB0;
+    io.rhoL1 = A1.redB1;
+    rc = inner_solve(p, lv, io, st);
+    if (rc) return rc;
+    rc = sum_to_planes(p, lv, Vh, st);
+    if (rc) return rc;
+    rc = run_fft(p, A2, +1, false, Vh, ST_C128, Vp, ST_C128, (int64_t)nb * 2, n3, nullptr, 1.0 / n2, 0,
+                 Wp, ST_C128, st);
+    if (rc) return rc;
+  }
+  // Outer step 2: r = C_1 v_b, w_b.
+  {
+    OuterMidArgs om;
+    om.nb = nb;
+    om.n2 = n2;
+    om.n3 = n3;
+    om.a = Vp;
+    om.c = nullptr;
+    om.r = Wp;
+    om.d1 = A1.bd;
+    om.w2 = w2;
+    om.h2 = A2.h;
+    om.h3 = p->hL;
+    om.k2Lo = make_double2(1.0, A2.lo ? -p->omega * A2.h : 0.0);
+    om.k2Hi = make_double2(1.0, A2.hi ? -p->omega * A2.h : 0.0);
+    om.k3Lo = p->kLo;
+    om.k3Hi = p->kHi;
+    HCHK(launch_outer_mid(om, st));
+    rc = run_fft(p, A2, -1, false, Wp, ST_C128, Rh, ST_C128, (int64_t)nb * 2, n3, A2.invmu, 1.0, 0, Vh,
+                 ST_C128, st);
+    if (rc) return rc;
+    InnerIO io;
+    io.sO = A1.sigA;
+    io.PO = Rh;
+    io.alpha0 = A1.va0d;
+    io.alpha1 = A1.va1d;
+    io.rhoL0 = A1.va0d;
+    io.rhoL1 = A1.va1d;
+    rc = inner_solve(p, lv, io, st);
+    if (rc) return rc;
+    rc = sum_to_planes(p, lv, Vh, st);
+    if (rc) return rc;
+    rc = run_fft(p, A2, +1, false, Vh, ST_C128, Wp, ST_C128, (int64_t)nb * 2, n3, nullptr, 1.0 / n2, 0,
+                 Rh, ST_C128, st);
+    if (rc) return rc;
+    // q = C_1 (v_b + w_b), transformed along x_2 and scaled by 1/mu_2
+    om.a = Vp;
+    om.c = Wp;
+    om.r = Vh;
+    HCHK(launch_outer_mid(om, st));
+    rc = run_fft(p, A2, -1, false, Vh, ST_C128, Rh, ST_C128, (int64_t)nb * 2, n3, A2.invmu, 1.0, 0, Wp,
+                 ST_C128, st);
+    if (rc) return rc;
+  }
+  // Outer step 3: corrected periodic solve, stored, then inverse transforms.
+  {
+    InnerIO io;
+    io.sO = A1.sigB;
+    io.in = W0;
+    io.in_kind = T;
+    io.PO = Rh;
+    io.alpha0 = A1.genB0;
+    io.alpha1 = A1.genB1;
+    io.out = W0;
+    io.out_kind = T;
+    rc = inner_solve(p, lv, io, st);
+    if (rc) return rc;
+  }
+  rc = run_fft(p, A2, +1, fp32, W0, T, W1, T, (int64_t)nb * n1, n3, nullptr, 1.0 / n2, 0, W2 == W1 ? W0 : W2,
+               T, st);
+  if (rc) return rc;
+  return run_fft(p, A1, +1, fp32, W1, T, u, ST_C128, nb, plane, nullptr, 1.0 / n1, accumulate, W2 == W1 ? W0 : W2,
+                 T, st);
+}
+
+int64_t npoints(const helm_plan* p) {
+  int64_t n = 1;
+  for (int j = 0; j < p->dim; ++j) n *= p->grid[j];
+  return n;
+}
+
+int ensure_workspace(helm_plan* p, int nb, bool fp32, bool need_r) {
+  const int64_t N = npoints(p);
+  const size_t esz = fp32 ? sizeof(float2) : sizeof(double2);
+  HCHK(p->W0.ensure((size_t)N * nb * esz));
+  HCHK(p->W1.ensure((size_t)N * nb * esz));
+  bool need_w2 = false;
+  if (p->dim == 3) need_w2 = p->ax[0].na > 1 || p->ax[1].na > 1;
+  if (need_w2) HCHK(p->W2.ensure((size_t)N * nb * esz));
+  if (need_r) HCHK(p->R.ensure((size_t)N * nb * (fp32 ? sizeof(float2) : sizeof(double2))));
+  // partial sums: max over the reductions used
+  size_t pe = 0;
+  if (p->dim == 2) {
+    pe = part_elems(1, nb, 1, p->ax[0].n, p->nL);
+  } else {
+    pe = std::max(part_elems(1, nb, p->ax[0].n, p->ax[1].n, p->nL),
+                  part_elems(2, nb, p->ax[0].n, p->ax[1].n, p->nL));
+  }
+  HCHK(p->part.ensure(pe * sizeof(double2)));
+  const int64_t nO = p->dim == 2 ? 1 : p->ax[0].n;
+  HCHK(p->VB.ensure((size_t)nb * nO * 2 * p->nL * sizeof(double2)));
+  HCHK(p->PIb.ensure((size_t)nb * nO * 2 * p->nL * sizeof(double2)));
+  if (p->dim == 3) {
+    const size_t pl = (size_t)nb * 2 * p->ax[1].n * p->nL * sizeof(double2);
+    HCHK(p->P0.ensure(pl));
+    HCHK(p->P1.ensure(pl));
+    HCHK(p->P2.ensure(pl));
+    HCHK(p->P3.ensure(pl));
+  }
+  HCHK(p->scratch.ensure((size_t)residual_scratch_len(p->dim, p->grid, nb) * sizeof(double)));
+  HCHK(p->norms.ensure((size_t)nb * 2 * sizeof(double)));
+  p->h_norms.resize(2 * nb);
+  return HELM_OK;
+}
+
+ResidArgs resid_args(helm_plan* p, int nb) {
+  ResidArgs a;
+  a.dim = p->dim;
+  a.nb = nb;
+  for (int j = 0; j < p->dim; ++j) {
+    a.ax[j].n = (int)p->grid[j];
+    a.ax[j].h = p->h[j];
+    const int lo = (p->abc >> (2 * j)) & 1, hi = (p->abc >> (2 * j + 1)) & 1;
+    a.ax[j].kLo = make_double2(1.0, lo ? -p->omega * p->h[j] : 0.0);
+    a.ax[j].kHi = make_double2(1.0, hi ? -p->omega * p->h[j] : 0.0);
+  }
+  a.w2 = p->omega * p->omega;
+  a.norms = p->norms.as<double>();
+  a.scratch = p->scratch.as<double>();
+  a.scratch_len = (int64_t)(p->scratch.bytes / sizeof(double));
+  a.r = nullptr;
+  a.r_kind = ST_C128;
+  return a;
+}
+
+// Residual norms -> host; returns max relative residual (NaN if non-finite).
+int residual_norms(helm_plan* p, const double2* u, const double2* f, void* r, int r_kind, int nb,
+                   hipStream_t st, double* relmax, std::vector<double>* rel) {
+  ResidArgs a = resid_args(p, nb);
+  a.u = u;
+  a.f = f;
+  a.r = r;
+  a.r_kind = r_kind;
+  HCHK(launch_residual(a, st));
+  HCHK(hipMemcpyAsync(p->h_norms.data(), a.norms, nb * 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+  HCHK(hipStreamSynchronize(st));
+  double mx = 0.0;
+  if (rel) rel->assign(nb, 0.0);
+  for (int b = 0; b < nb; ++b) {
+    const double rr = p->h_norms[2 * b], ff = p->h_norms[2 * b + 1];
+    if (!std::isfinite(rr) || !std::isfinite(ff)) {
+      *relmax = NAN;
+      return HELM_ENONFINITE;
+    }
+    const double v = ff > 0 ? std::sqrt(rr / ff) : 0.0;
+    if (rel) (*rel)[b] = v;
+    mx = std::max(mx, v);
+  }
+  *relmax = mx;
+  return HELM_OK;
+}
+
+void fill_axis_tables_host(PAxis& a, double omega, std::vector<double2>& buf, std::vector<double>& invmu) {
+  const int n = a.n;
+  const double h = a.h;
+  buf.assign((size_t)n * 8, make_double2(0, 0));
+  invmu.assign(n, 0.0);
+  for (int l = 0; l < n; ++l) {
+    const double th = 2.0 * M_PI * l / n;
+    const double sh = std::sin(0.5 * th);
+    const double omc = 2.0 * sh * sh;  // 1 - cos(theta) without cancellation
+    const double cth = 1.0 - omc;
+    const double mu = h / 6.0 * (4.0 + 2.0 * cth);
+    const double lamB = 6.0 * omc / (h * h * (2.0 + cth));
+    const double c = std::cos(th), s = std::sin(th);
+    buf[0 * n + l] = make_double2(lamB, 0.0);                              // sigB
+    buf[1 * n + l] = hd2(a.lamA[l]);                                       // sigA
+    buf[2 * n + l] = make_double2(1.0 / mu, 0.0);                          // genB0
+    buf[3 * n + l] = make_double2(c / mu, s / mu);                         // genB1 = e^{+i th}/mu
+    buf[4 * n + l] = make_double2(1.0 / n, 0.0);                           // redB0
+    buf[5 * n + l] = make_double2(c / n, -s / n);                          // redB1 = e^{-i th}/n
+    buf[6 * n + l] = hd2(a.va0[l]);
+    buf[7 * n + l] = hd2(a.va1[l]);
+    invmu[l] = 1.0 / mu;
+  }
+  // B - A on the two end nodes of this axis
+  a.bd.dK[0][0] = make_double2(1.0 / h, a.lo ? omega : 0.0);
+  a.bd.dK[1][1] = make_double2(1.0 / h, a.hi ? omega : 0.0);
+  a.bd.dK[0][1] = a.bd.dK[1][0] = make_double2(-1.0 / h, 0.0);
+  a.bd.dM[0][0] = a.bd.dM[1][1] = 2.0 * h / 6.0;
+  a.bd.dM[0][1] = a.bd.dM[1][0] = h / 6.0;
+  (void)omega;
+}
+
+}  // namespace
+
+}  // namespace helm
+
+using namespace helm;
+
+extern "C" {
+
+void helm_default_options(helm_options* opt) {
+  if (!opt) return;
+  opt->precision = HELM_PREC_FP64;
+  opt->tol = 1e-10;
+  opt->max_iter = 8;
+  opt->check = 1;
+}
+
+const char* helm_strerror(int code) {
+  switch (code) {
+    case HELM_OK: return "success";
+    case HELM_EINVAL: return "invalid argument";
+    case HELM_ENOMEM: return "out of memory";
+    case HELM_EDEVICE: return "HIP device error";
+    case HELM_ESINGULAR: return "singular system";
+    case HELM_ENOCONV: return "refinement did not converge";
+    case HELM_ENONFINITE: return "non-finite value in right-hand side or residual";
+    case HELM_EUNSUPPORTED: return "unsupported problem for this build";
+    default: return "unknown status";
+  }
+}
+
+int helm_setup(int dim, const int64_t* grid, const double* h, double omega, uint32_t abc,
+               const helm_options* opt, helm_plan** out) {
+  if (!out || !grid || !h || (dim != 2 && dim != 3)) return HELM_EINVAL;
+  *out = nullptr;
+  for (int j = 0; j < dim; ++j)
+    if (grid[j] < 3 || grid[j] > (1 << 24) || !(h[j] > 0.0) || !std::isfinite(h[j])) return HELM_EINVAL;
+  if (!std::isfinite(omega)) return HELM_EINVAL;
+  if (abc >> (2 * dim)) return HELM_EINVAL;
+  if (omega == 0.0) return HELM_ESINGULAR;  // absorbing faces degenerate to Neumann: constants in the kernel
+  const int last = dim - 1;
+  if (!((abc >> (2 * last)) & 3)) return HELM_EUNSUPPORTED;  // last axis needs an absorbing face
+  std::unique_ptr<helm_plan> p(new (std::nothrow) helm_plan());
+  if (!p) return HELM_ENOMEM;
+  p->dim = dim;
+  p->omega = omega;
+  p->abc = abc;
+  helm_default_options(&p->opt);
+  if (opt) p->opt = *opt;
+  if (p->opt.precision != HELM_PREC_FP64 && p->opt.precision != HELM_PREC_MIXED) return HELM_EINVAL;
+  if (p->opt.max_iter < 0 || !(p->opt.tol >= 0.0)) return HELM_EINVAL;
+  for (int j = 0; j < dim; ++j) {
+    p->grid[j] = grid[j];
+    p->h[j] = h[j];
+  }
+  if (hipGetDevice(&p->device) != hipSuccess) return HELM_EDEVICE;
+  p->nper = dim - 1;
+  p->nL = (int)grid[last];
+  p->hL = h[last];
+  p->kLo = make_double2(1.0, ((abc >> (2 * last)) & 1) ? -omega * h[last] : 0.0);
+  p->kHi = make_double2(1.0, ((abc >> (2 * last + 1)) & 1) ? -omega * h[last] : 0.0);
+  if (p->nL > 4096) return HELM_EUNSUPPORTED;
+  for (int j = 0; j < p->nper; ++j) {
+    PAxis& a = p->ax[j];
+    a.n = (int)grid[j];
+    a.h = h[j];
+    a.lo = (abc >> (2 * j)) & 1;
+    a.hi = (abc >> (2 * j + 1)) & 1;
+    if (!is_pow2(a.n)) return HELM_EUNSUPPORTED;
+    if (a.n <= 512) {
+      a.na = 1;
+      a.nbp = a.n;
+    } else {
+      int nb = 1;
+      while ((int64_t)nb * nb < a.n) nb <<= 1;
+      a.nbp = nb;
+      a.na = a.n / nb;
+      if (a.na > 512 || a.nbp > 512) return HELM_EUNSUPPORTED;
+    }
+    const int st = eig1d(a.n, a.h, omega, a.lo, a.hi, a.lamA, a.va0, a.va1);
+    if (st != HELM_OK) return st;
+    std::vector<double2> buf;
+    std::vector<double> invmu;
+    fill_axis_tables_host(a, omega, buf, invmu);
+    const size_t nb2 = (size_t)a.n * 8 * sizeof(double2);
+    if (a.tab.ensure(nb2 + (size_t)a.n * sizeof(double)) != hipSuccess) return HELM_ENOMEM;
+    if (upload(a.tab.p, buf.data(), nb2) != hipSuccess) return HELM_EDEVICE;
+    if (upload((char*)a.tab.p + nb2, invmu.data(), (size_t)a.n * sizeof(double)) != hipSuccess)
+      return HELM_EDEVICE;
+    double2* t = a.tab.as<double2>();
+    a.sigB = t;
+    a.sigA = t + a.n;
+    a.genB0 = t + 2 * a.n;
+    a.genB1 = t + 3 * a.n;
+    a.redB0 = t + 4 * a.n;
+    a.redB1 = t + 5 * a.n;
+    a.va0d = t + 6 * a.n;
+    a.va1d = t + 7 * a.n;
+    a.invmu = reinterpret_cast<double*>((char*)a.tab.p + nb2);
+  }
+  p->rep.status = HELM_OK;
+  p->rep.rel_residual_max = -1;
+  p->rep.rel_residual_first = -1;
+  *out = p.release();
+  return HELM_OK;
+}
+
+int helm_solve(helm_plan* p, const void* f, void* u, int nrhs, void* stream) {
+  if (!p || !f || !u || nrhs < 1) return HELM_EINVAL;
+  if (f == u) return HELM_EINVAL;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  const bool mixed = p->opt.precision == HELM_PREC_MIXED;
+  const bool check = mixed || p->opt.check;
+  helm_report& rep = p->rep;
+  rep = helm_report{};
+  rep.precision = p->opt.precision;
+  rep.nrhs = nrhs;
+  rep.rel_residual_max = -1;
+  rep.rel_residual_first = -1;
+  int rc = ensure_workspace(p, nrhs, mixed, check);
+  if (rc) return rep.status = rc;
+  const double2* F = reinterpret_cast<const double2*>(f);
+  double2* U = reinterpret_cast<double2*>(u);
+  rc = solve_once(p, f, ST_C128, U, 0, nrhs, mixed, st);
+  if (rc) return rep.status = rc;
+  if (!check) return rep.status = HELM_OK;
+  const int rk = mixed ? ST_C64 : ST_C128;
+  double rel = 0;
+  rc = residual_norms(p, U, F, p->R.p, rk, nrhs, st, &rel, nullptr);
+  rep.rel_residual_first = rel;
+  rep.rel_residual_max = rel;
+  if (rc) return rep.status = rc;
+  int it = 0;
+  while (rel > p->opt.tol && it < p->opt.max_iter) {
+    rc = solve_once(p, p->R.p, rk, U, 1, nrhs, mixed, st);
+    if (rc) return rep.status = rc;
+    ++it;
+    double nrel = 0;
+    rc = residual_norms(p, U, F, p->R.p, rk, nrhs, st, &nrel, nullptr);
+    rep.iterations = it;
+    rep.rel_residual_max = nrel;
+    if (rc) return rep.status = rc;
+    if (!(nrel < 0.5 * rel)) {
+      rel = nrel;
+      break;  // stagnation
+    }
+    rel = nrel;
+  }
+  rep.status = rel <= p->opt.tol ? HELM_OK : HELM_ENOCONV;
+  return rep.status;
+}
+
+int helm_report_get(const helm_plan* p, helm_report* out) {
+  if (!p || !out) return HELM_EINVAL;
+  *out = p->rep;
+  return HELM_OK;
+}
+
+int helm_residual(helm_plan* p, const void* u, const void* f, void* r, double* rel_res, int nrhs,
+                  void* stream) {
+  if (!p || !u || !f || !rel_res || nrhs < 1) return HELM_EINVAL;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  const int64_t N = npoints(p);
+  if (p->scratch.ensure((size_t)residual_scratch_len(p->dim, p->grid, nrhs) * sizeof(double)) != hipSuccess)
+    return HELM_ENOMEM;
+  if (p->norms.ensure((size_t)nrhs * 2 * sizeof(double)) != hipSuccess) return HELM_ENOMEM;
+  p->h_norms.resize(2 * nrhs);
+  (void)N;
+  double mx = 0;
+  std::vector<double> rel;
+  const int rc = residual_norms(p, reinterpret_cast<const double2*>(u), reinterpret_cast<const double2*>(f), r,
+                                ST_C128, nrhs, st, &mx, &rel);
+  for (int b = 0; b < nrhs; ++b) rel_res[b] = rc == HELM_OK ? rel[b] : NAN;
+  return rc;
+}
+
+void helm_destroy(helm_plan* p) {
+  if (!p) return;
+  (void)hipDeviceSynchronize();
+  delete p;
+}
+
+}  // extern "C"

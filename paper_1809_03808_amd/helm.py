@@ -1,0 +1,209 @@
+"""ctypes binding of libhelm.so (C ABI in include/helm.h).
+
+Argument marshalling only: every step of a solve runs in the HIP library.
+Device arrays are torch tensors (complex128, contiguous, on the plan's
+device); their data_ptr() and the current torch stream are passed through.
+If the library has not been built, ``lib()`` raises: there is no fallback.
+"""
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhelm.so")
+
+HELM_OK = 0
+HELM_EINVAL = -1
+HELM_ENOMEM = -2
+HELM_EDEVICE = -3
+HELM_ESINGULAR = -4
+HELM_ENOCONV = -5
+HELM_ENONFINITE = -6
+HELM_EUNSUPPORTED = -7
+
+PREC_FP64 = 0
+PREC_MIXED = 1
+
+# Every symbol declared in include/helm.h.
+EXPORTS = (
+    "helm_default_options", "helm_setup", "helm_solve", "helm_report_get",
+    "helm_residual", "helm_destroy", "helm_strerror", "helm_eig1d",
+)
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int), ("tol", ctypes.c_double),
+                ("max_iter", ctypes.c_int), ("check", ctypes.c_int)]
+
+
+class Report(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("iterations", ctypes.c_int),
+                ("precision", ctypes.c_int), ("nrhs", ctypes.c_int),
+                ("rel_residual_max", ctypes.c_double),
+                ("rel_residual_first", ctypes.c_double)]
+
+
+class HelmError(RuntimeError):
+    def __init__(self, code, where):
+        self.code = code
+        super().__init__(f"{where}: {strerror(code)} ({code})")
+
+
+_lib = None
+
+
+def lib():
+    """Load libhelm.so (raises OSError if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise OSError(f"{LIB_PATH} not found: build it with `python -m paper_1809_03808_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i64p, dp = ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)
+    L.helm_default_options.argtypes = [ctypes.POINTER(Options)]
+    L.helm_default_options.restype = None
+    L.helm_setup.argtypes = [ctypes.c_int, i64p, dp, ctypes.c_double, ctypes.c_uint32,
+                             ctypes.POINTER(Options), ctypes.POINTER(vp)]
+    L.helm_setup.restype = ctypes.c_int
+    L.helm_solve.argtypes = [vp, vp, vp, ctypes.c_int, vp]
+    L.helm_solve.restype = ctypes.c_int
+    L.helm_report_get.argtypes = [vp, ctypes.POINTER(Report)]
+    L.helm_report_get.restype = ctypes.c_int
+    L.helm_residual.argtypes = [vp, vp, vp, vp, dp, ctypes.c_int, vp]
+    L.helm_residual.restype = ctypes.c_int
+    L.helm_destroy.argtypes = [vp]
+    L.helm_destroy.restype = None
+    L.helm_strerror.argtypes = [ctypes.c_int]
+    L.helm_strerror.restype = ctypes.c_char_p
+    L.helm_eig1d.argtypes = [ctypes.c_int64, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                             ctypes.c_int, dp, dp]
+    L.helm_eig1d.restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def strerror(code):
+    return lib().helm_strerror(int(code)).decode()
+
+
+def abc_mask(abc):
+    """Per-axis (lo, hi) booleans -> face bit mask (bit 2j low, 2j+1 high)."""
+    m = 0
+    for j, (lo, hi) in enumerate(abc):
+        m |= (1 if lo else 0) << (2 * j)
+        m |= (1 if hi else 0) << (2 * j + 1)
+    return m
+
+
+def eig1d(n, h, omega, abc_lo=True, abc_hi=True):
+    """Host FP64 eigen-setup: (lambda[n] complex, vb[2][n] complex)."""
+    lam = np.zeros(2 * n)
+    vb = np.zeros(4 * n)
+    rc = lib().helm_eig1d(int(n), float(h), float(omega), int(bool(abc_lo)), int(bool(abc_hi)),
+                          lam.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                          vb.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    if rc != HELM_OK:
+        raise HelmError(rc, "helm_eig1d")
+    lam = lam.view(np.complex128)
+    vb = vb.view(np.complex128).reshape(2, n)
+    return lam, vb
+
+
+def _stream_ptr(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _check_tensor(t, grid, name):
+    import torch
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.complex128 or not t.is_cuda:
+        raise TypeError(f"{name} must be a complex128 CUDA/HIP tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if tuple(t.shape[-len(grid):]) != tuple(grid):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, grid is {tuple(grid)}")
+    return 1 if t.dim() == len(grid) else int(np.prod(t.shape[:-len(grid)]))
+
+
+class Plan:
+    """A solver plan: ``Plan(grid, h, omega, abc)`` then ``plan.solve(f, u)``."""
+
+    def __init__(self, grid, h, omega, abc=None, precision=PREC_FP64, tol=1e-10, max_iter=8,
+                 check=True):
+        L = lib()
+        self.grid = tuple(int(n) for n in grid)
+        self.dim = len(self.grid)
+        self.h = tuple(float(x) for x in h)
+        self.omega = float(omega)
+        if abc is None:
+            abc = (1 << (2 * self.dim)) - 1
+        self.abc = abc if isinstance(abc, int) else abc_mask(abc)
+        opt = Options()
+        L.helm_default_options(ctypes.byref(opt))
+        opt.precision = int(precision)
+        opt.tol = float(tol)
+        opt.max_iter = int(max_iter)
+        opt.check = int(bool(check))
+        g = (ctypes.c_int64 * self.dim)(*self.grid)
+        hh = (ctypes.c_double * self.dim)(*self.h)
+        out = ctypes.c_void_p()
+        rc = L.helm_setup(self.dim, g, hh, self.omega, ctypes.c_uint32(self.abc), ctypes.byref(opt),
+                          ctypes.byref(out))
+        if rc != HELM_OK:
+            raise HelmError(rc, "helm_setup")
+        self._p = out
+
+    def solve(self, f, u, stream=None, raise_on_error=True):
+        """u = A^{-1} f (device tensors [nrhs][grid] or [grid]).  Returns the status."""
+        nrhs = _check_tensor(f, self.grid, "f")
+        if _check_tensor(u, self.grid, "u") != nrhs:
+            raise ValueError("f and u hold different numbers of right-hand sides")
+        rc = lib().helm_solve(self._p, ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(u.data_ptr()),
+                              nrhs, _stream_ptr(stream))
+        if rc != HELM_OK and raise_on_error:
+            raise HelmError(rc, "helm_solve")
+        return rc
+
+    def report(self):
+        r = Report()
+        rc = lib().helm_report_get(self._p, ctypes.byref(r))
+        if rc != HELM_OK:
+            raise HelmError(rc, "helm_report_get")
+        return {k: getattr(r, k) for k, _ in Report._fields_}
+
+    def residual(self, u, f, r=None, stream=None):
+        """FP64 r = f - A u on the device; returns per-RHS ||r||/||f||."""
+        nrhs = _check_tensor(f, self.grid, "f")
+        _check_tensor(u, self.grid, "u")
+        if r is not None:
+            _check_tensor(r, self.grid, "r")
+        rel = np.zeros(nrhs)
+        rc = lib().helm_residual(self._p, ctypes.c_void_p(u.data_ptr()), ctypes.c_void_p(f.data_ptr()),
+                                 ctypes.c_void_p(r.data_ptr() if r is not None else 0),
+                                 rel.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), nrhs,
+                                 _stream_ptr(stream))
+        if rc != HELM_OK:
+            raise HelmError(rc, "helm_residual")
+        return rel
+
+    def close(self):
+        if getattr(self, "_p", None):
+            lib().helm_destroy(self._p)
+            self._p = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()

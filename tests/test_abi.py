@@ -1,0 +1,60 @@
+"""The C-ABI library loads without a GPU and exports every symbol that
+include/helm.h declares (no compute calls here)."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1809_03808_amd import helm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "helm.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(helm_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for n in ("helm_setup", "helm_solve", "helm_report_get", "helm_residual", "helm_destroy",
+              "helm_strerror", "helm_eig1d", "helm_default_options"):
+        assert n in names
+    assert set(names) == set(helm.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    L = ctypes.CDLL(helm.LIB_PATH)
+    for name in declared_functions():
+        assert hasattr(L, name), name
+
+
+def test_strerror_and_defaults():
+    assert helm.strerror(0) == "success"
+    assert "singular" in helm.strerror(helm.HELM_ESINGULAR)
+    opt = helm.Options()
+    helm.lib().helm_default_options(ctypes.byref(opt))
+    assert opt.precision == helm.PREC_FP64 and opt.tol == 1e-10 and opt.max_iter == 8 and opt.check == 1
+
+
+def test_eig1d_rejects_bad_arguments():
+    with pytest.raises(helm.HelmError) as e:
+        helm.eig1d(2, 0.5, 1.0)
+    assert e.value.code == helm.HELM_EINVAL
+
+
+@pytest.mark.parametrize("grid,h,omega,mask,code", [
+    ((16, 16), (1 / 15, 1 / 15), 0.0, 0b1111, helm.HELM_ESINGULAR),
+    ((16, 2), (1 / 15, 1.0), 3.0, 0b1111, helm.HELM_EINVAL),
+    ((16, 16), (1 / 15, -1.0), 3.0, 0b1111, helm.HELM_EINVAL),
+    ((16, 16), (1 / 15, 1 / 15), 3.0, 0b0011, helm.HELM_EUNSUPPORTED),  # last axis all Neumann
+    ((16, 16, 16), (0.1,) * 3, float("nan"), 0b111111, helm.HELM_EINVAL),
+])
+def test_setup_argument_errors(grid, h, omega, mask, code):
+    """Validation happens on the host before any device call."""
+    with pytest.raises(helm.HelmError) as e:
+        helm.Plan(grid, h, omega, mask)
+    assert e.value.code == code

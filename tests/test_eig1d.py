@@ -1,0 +1,53 @@
+"""Host FP64 eigen-setup of the library (helm_eig1d, no GPU) against the
+dense QZ eigen-oracle, and against identities at sizes QZ is too slow for."""
+
+import numpy as np
+import pytest
+
+from oracle import eigen, fem
+from paper_1809_03808_amd import helm
+
+
+def _match(lam_a, lam_b):
+    """Pair each eigenvalue of a with the nearest of b; return (perm, max rel err)."""
+    perm = np.array([np.argmin(np.abs(lam_b - x)) for x in lam_a])
+    assert len(set(perm.tolist())) == len(lam_a), "eigenvalues did not pair one-to-one"
+    err = np.max(np.abs(lam_a - lam_b[perm]) / np.abs(lam_b[perm]).clip(1.0))
+    return perm, err
+
+
+@pytest.mark.parametrize("n,ppw,lo,hi", [
+    (8, 10.0, True, True), (33, 10.0, True, True), (64, 8.0, True, True),
+    (128, 10.0, True, True), (256, 20.0, True, True), (100, 12.0, True, False),
+    (65, 9.0, False, True), (40, 10.0, False, False),
+])
+def test_eig1d_matches_qz_oracle(n, ppw, lo, hi):
+    h = 1.0 / (n - 1)
+    w = 2 * np.pi * (n - 1) / ppw
+    lam, vb = helm.eig1d(n, h, w, lo, hi)
+    lam_o, V_o = eigen.abc_pencil(n, h, w, lo, hi)
+    perm, err = _match(lam, lam_o)
+    assert err < 1e-10, err
+    # boundary rows up to the sign of each column: compare sign-free products
+    v0o, v1o = V_o[0, perm], V_o[-1, perm]
+    scale = np.max(np.abs(v0o)) ** 2
+    assert np.max(np.abs(vb[0] * vb[1] - v0o * v1o)) < 1e-8 * scale
+    assert np.max(np.abs(vb[0] ** 2 - v0o ** 2)) < 1e-8 * scale
+    assert np.max(np.abs(vb[1] ** 2 - v1o ** 2)) < 1e-8 * scale
+
+
+@pytest.mark.parametrize("n,ppw", [(1024, 10.0), (2048, 10.0)])
+def test_eig1d_large_identities(n, ppw):
+    """n distinct eigenvalues whose sum is trace(M^{-1} K), all with
+    Im < 0 (v^H K v has imaginary part -w(|v_0|^2 + |v_{n-1}|^2))."""
+    h = 1.0 / (n - 1)
+    w = 2 * np.pi * (n - 1) / ppw
+    lam, vb = helm.eig1d(n, h, w)
+    K = fem.stiffness_1d(n, h, w, True, True)
+    M = fem.mass_1d(n, h)
+    tr = np.trace(np.linalg.solve(M, K))
+    assert abs(lam.sum() - tr) < 1e-11 * abs(tr)
+    assert lam.imag.max() < 0
+    d = np.abs(lam[:, None] - lam[None, :]) + np.eye(n) * 1e300
+    assert d.min() > 1.0
+    assert np.all(np.isfinite(vb))

@@ -1,0 +1,150 @@
+"""GPU parity of the fast solver (through the C ABI) against the CPU oracle.
+
+Small and ragged grids are compared element by element with the banded-LU
+oracle; the bar is relative error <= 1e-9 for the FP64 path and relative
+residual <= 1e-10 (plus error <= 1e-8) for the mixed-precision refined path.
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import fem
+from paper_1809_03808_amd import helm, inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def _abc_tuple(dim, mask):
+    return tuple(((mask >> (2 * j)) & 1 == 1, (mask >> (2 * j + 1)) & 1 == 1) for j in range(dim))
+
+
+def _run(grid, omega, mask, f, precision=helm.PREC_FP64, check=True):
+    grid = tuple(grid)
+    h = inputs.spacing(grid)
+    _say("case", grid, omega, bin(mask), "prec", precision, "nrhs", f.shape[0])
+    plan = helm.Plan(grid, h, omega, mask, precision=precision, check=check)
+    fd = torch.from_numpy(f).to("cuda")
+    ud = torch.empty_like(fd)
+    rc = plan.solve(fd, ud, raise_on_error=False)
+    torch.cuda.synchronize()
+    rep = plan.report()
+    u = ud.cpu().numpy()
+    plan.close()
+    return rc, rep, u, h
+
+
+def _oracle(grid, h, omega, mask, f):
+    return fem.solve(tuple(grid), h, omega, _abc_tuple(len(grid), mask),
+                     f.reshape(f.shape[0], -1)).reshape(f.shape)
+
+
+CASES_2D = [
+    ((16, 13), 10.0, 0b1111),
+    ((32, 47), 25.0, 0b1111),
+    ((64, 100), 40.0, 0b1111),
+    ((8, 5), 3.0, 0b1111),
+    ((32, 33), 20.0, 0b1100),   # x1 both Neumann
+    ((64, 41), 30.0, 0b0110),   # mixed faces on both axes
+    ((1024, 21), 400.0, 0b1111),  # two-pass transform along x1
+]
+
+
+@pytest.mark.parametrize("grid,omega,mask", CASES_2D)
+def test_2d_fp64_matches_banded_lu(grid, omega, mask):
+    f = inputs.gaussian_batch(grid, [11, 12]).astype(np.complex128)
+    rc, rep, u, h = _run(grid, omega, mask, f)
+    ref = _oracle(grid, h, omega, mask, f)
+    err = fem.rel_error(u.reshape(2, -1), ref.reshape(2, -1))
+    _say("  rel err", err, "report", rep)
+    assert rc == helm.HELM_OK
+    assert np.max(err) <= 1e-9
+    assert rep["rel_residual_max"] <= 1e-10
+
+
+def test_c1_128_omega80_point_source():
+    """The 128x128, omega = 80 workload (~10 points per wavelength): Gaussian
+    load plus a centred point source, FP64, against banded LU."""
+    w = inputs.workload("2d_128_w80")
+    grid = w["grid"]
+    f = (inputs.gaussian(grid, inputs.rhs_seed(1, 0, 0)) + inputs.point_source(grid))[None]
+    rc, rep, u, h = _run(grid, w["omega"], inputs.ALL_ABC_2D, f)
+    ref = _oracle(grid, h, w["omega"], inputs.ALL_ABC_2D, f)
+    err = fem.rel_error(u.reshape(1, -1), ref.reshape(1, -1))
+    res = fem.rel_residual(grid, h, w["omega"], _abc_tuple(2, inputs.ALL_ABC_2D), u.reshape(1, -1),
+                           f.reshape(1, -1))
+    _say("  C1 rel err", err, "oracle residual", res, rep)
+    assert rc == helm.HELM_OK
+    assert err[0] <= 1e-9
+    assert res[0] <= 1e-10
+
+
+CASES_3D = [
+    ((8, 8, 9), 6.0, 0b111111),
+    ((16, 8, 13), 12.0, 0b111111),
+    ((8, 16, 7), 10.0, 0b110111),  # x2 low face Neumann
+    ((16, 16, 16), 15.0, 0b111111),
+]
+
+
+@pytest.mark.parametrize("grid,omega,mask", CASES_3D)
+def test_3d_fp64_matches_banded_lu(grid, omega, mask):
+    f = inputs.gaussian_batch(grid, [21, 22]).astype(np.complex128)
+    rc, rep, u, h = _run(grid, omega, mask, f)
+    ref = _oracle(grid, h, omega, mask, f)
+    err = fem.rel_error(u.reshape(2, -1), ref.reshape(2, -1))
+    _say("  rel err", err, "report", rep)
+    assert rc == helm.HELM_OK
+    assert np.max(err) <= 1e-9
+
+
+@pytest.mark.parametrize("grid,omega", [((64, 77), 35.0), ((16, 16, 13), 14.0), ((1024, 17), 300.0)])
+def test_mixed_precision_refines_to_1e10(grid, omega):
+    mask = (1 << (2 * len(grid))) - 1
+    f = inputs.gaussian_batch(grid, [31, 32, 33]).astype(np.complex128)
+    rc, rep, u, h = _run(grid, omega, mask, f, precision=helm.PREC_MIXED)
+    ref = _oracle(grid, h, omega, mask, f)
+    err = fem.rel_error(u.reshape(3, -1), ref.reshape(3, -1))
+    res = fem.rel_residual(tuple(grid), h, omega, _abc_tuple(len(grid), mask), u.reshape(3, -1),
+                           f.reshape(3, -1))
+    _say("  mixed rel err", err, "oracle residual", res, rep)
+    assert rc == helm.HELM_OK
+    assert rep["iterations"] >= 1
+    assert np.max(res) <= 1e-10
+    assert np.max(err) <= 1e-8
+
+
+@pytest.mark.parametrize("grid", [(16, 11), (8, 8, 5)])
+def test_residual_kernel_matches_oracle(grid):
+    grid = tuple(grid)
+    mask = (1 << (2 * len(grid))) - 1
+    omega = 7.0
+    h = inputs.spacing(grid)
+    u = inputs.gaussian_batch(grid, [41, 42])
+    f = inputs.gaussian_batch(grid, [43, 44])
+    plan = helm.Plan(grid, h, omega, mask)
+    ud = torch.from_numpy(u).cuda()
+    fd = torch.from_numpy(f).cuda()
+    rd = torch.empty_like(ud)
+    rel = plan.residual(ud, fd, rd)
+    plan.close()
+    r = rd.cpu().numpy().reshape(2, -1)
+    ref = fem.residual(grid, h, omega, _abc_tuple(len(grid), mask), u.reshape(2, -1), f.reshape(2, -1))
+    assert np.max(np.abs(r - ref)) <= 1e-12 * np.max(np.abs(ref))
+    assert np.allclose(rel, np.linalg.norm(ref, axis=1) / np.linalg.norm(f.reshape(2, -1), axis=1),
+                       rtol=1e-12)
+
+
+def test_nonfinite_rhs_reported():
+    grid = (16, 9)
+    f = inputs.gaussian_batch(grid, [51])
+    f[0, 3, 4] = np.nan
+    rc, rep, u, h = _run(grid, 8.0, 0b1111, f)
+    assert rc == helm.HELM_ENONFINITE
