@@ -127,6 +127,28 @@ int helm_report_get(const helm_plan* p, helm_report* out);
 int helm_residual(helm_plan* p, const void* u, const void* f, void* r,
                   double* rel_res, int nrhs, void* stream);
 
+/*
+ * Per-kernel timing.  With helm_profile(p, 1) every kernel launch of later
+ * solves on this plan is bracketed by two HIP events recorded on the solve's
+ * stream; helm_kernel_stats_get synchronises on the last event and returns,
+ * per kernel function, the summed event time (ms), the number of launches and
+ * the summed algorithmic bytes (the N-sized arrays each launch must read and
+ * write once: 2 x element size per unknown for a transform pass, 1x, 0x or 2x
+ * for the Step 1 / Step 2 / Step 3 line solves, 32 bytes for the FP64
+ * residual).  reset != 0 clears the accumulators afterwards.
+ */
+#define HELM_NKERNELS 8
+typedef struct helm_kernel_stats {
+    double ms[HELM_NKERNELS];
+    double bytes[HELM_NKERNELS];
+    int    calls[HELM_NKERNELS];
+} helm_kernel_stats;
+
+int helm_profile(helm_plan* p, int on);
+int helm_kernel_stats_get(helm_plan* p, helm_kernel_stats* out, int reset);
+/* Name of kernel slot k (the device function timed in that slot), or NULL. */
+const char* helm_kernel_name(int k);
+
 /* Release the plan and its device memory (synchronises the device first). */
 void helm_destroy(helm_plan* p);
 

@@ -47,7 +47,7 @@ def build(verbose=False):
     for s in CXX_SOURCES:
         o = os.path.join(BUILD, s + ".o")
         objs.append(o)
-        jobs.append(["g++", "-O3", "-std=c++17", "-fPIC", "-fopenmp", "-Wall", *inc,
+        jobs.append(["g++", "-O3", "-std=c++17", "-fPIC", "-fopenmp", "-fcx-fortran-rules", "-Wall", *inc,
                      "-c", os.path.join(CSRC, s), "-o", o])
     hipcc = os.path.join(ROCM, "bin", "hipcc")
     for s in HIP_SOURCES:

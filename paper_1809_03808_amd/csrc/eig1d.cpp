@@ -14,7 +14,8 @@
 //      ratio form r_i = u_i'/u_i so that nothing overflows;
 //   2. each root refined by inverse iteration with the complex-symmetric
 //      Rayleigh quotient lambda = x^T K x / x^T M x, using Gaussian
-//      elimination with partial pivoting on the tridiagonal K - lambda M;
+//      elimination with partial pivoting on the tridiagonal K - lambda M,
+//      in x87 extended precision with a cancellation-free x^T K x;
 //   3. each eigenvector scaled by (v^T M v)^{-1/2}.
 // With both faces Neumann (or omega = 0) the spectrum is the closed-form
 // cosine one, 6(1 - cos t)/(h^2 (2 + cos t)), t = k pi/(n - 1), used directly
@@ -77,52 +78,100 @@ cd log_derivative(const Pencil& P, cd lam) {
   return s;
 }
 
+// The refinement runs in x87 extended precision (64-bit significand): for the
+// smooth low modes the FP64 Rayleigh quotient and inverse iteration lose
+// about 1e-11 relative to cancellation, and the fast solver's FP64 residual is
+// sensitive to that (it rounds eigenvalues to FP64 afterwards).
+using xr = long double;
+using xc = std::complex<long double>;
+
 // Solve the tridiagonal system (dl, d, du) x = b by Gaussian elimination
 // with partial pivoting (row interchanges produce a second super-diagonal).
 // Arrays are overwritten.  A zero pivot is replaced by a tiny value: the
 // callers are inverse iterations, where a (near-)singular matrix is the point.
-void tri_solve_pp(std::vector<cd>& dl, std::vector<cd>& d, std::vector<cd>& du,
-                  std::vector<cd>& b, std::vector<cd>& x, double tiny) {
+void tri_solve_pp(std::vector<xc>& dl, std::vector<xc>& d, std::vector<xc>& du,
+                  std::vector<xc>& b, std::vector<xc>& x, xr tiny) {
   const int n = (int)d.size();
-  std::vector<cd> du2(n, cd(0.0));
+  std::vector<xc> du2(n, xc(0.0L));
   for (int i = 0; i + 1 < n; ++i) {
     if (std::abs(d[i]) >= std::abs(dl[i])) {
-      if (d[i] == cd(0.0)) d[i] = tiny;
-      const cd fct = dl[i] / d[i];
+      if (d[i] == xc(0.0L)) d[i] = tiny;
+      const xc fct = dl[i] / d[i];
       d[i + 1] -= fct * du[i];
       b[i + 1] -= fct * b[i];
-      du2[i] = 0.0;
+      du2[i] = 0.0L;
     } else {
-      const cd fct = d[i] / dl[i];
+      const xc fct = d[i] / dl[i];
       d[i] = dl[i];
-      const cd tmp = d[i + 1];
+      const xc tmp = d[i + 1];
       d[i + 1] = du[i] - fct * tmp;
       if (i + 2 < n) {
         du2[i] = du[i + 1];
         du[i + 1] = -fct * du2[i];
       }
       du[i] = tmp;
-      const cd tb = b[i];
+      const xc tb = b[i];
       b[i] = b[i + 1];
       b[i + 1] = tb - fct * b[i + 1];
     }
   }
-  if (d[n - 1] == cd(0.0)) d[n - 1] = tiny;
+  if (d[n - 1] == xc(0.0L)) d[n - 1] = tiny;
   x[n - 1] = b[n - 1] / d[n - 1];
   if (n > 1) x[n - 2] = (b[n - 2] - du[n - 2] * x[n - 1]) / d[n - 2];
   for (int i = n - 3; i >= 0; --i) x[i] = (b[i] - du[i] * x[i + 1] - du2[i] * x[i + 2]) / d[i];
 }
 
-cd quad_form(const Pencil& P, const std::vector<cd>& x, bool stiffness) {
-  cd s = 0.0, o = 0.0;
-  for (int i = 0; i < P.n; ++i) s += (stiffness ? P.ka[i] : cd(P.ma[i])) * x[i] * x[i];
-  for (int i = 0; i + 1 < P.n; ++i) o += x[i] * x[i + 1];
-  return s + 2.0 * (stiffness ? P.kb : P.mb) * o;
+// The pencil in extended precision, built from the same double inputs.
+struct XPencil {
+  int n;
+  xr h, w;
+  int lo, hi;
+  std::vector<xc> ka;
+  std::vector<xr> ma;
+  xr kb, mb;
+};
+
+XPencil make_xpencil(int n, double h, double omega, int lo, int hi) {
+  XPencil P;
+  P.n = n;
+  P.h = h;
+  P.w = omega;
+  P.lo = lo;
+  P.hi = hi;
+  P.ka.assign(n, xc(2.0L / P.h, 0.0L));
+  P.ma.assign(n, 4.0L * P.h / 6.0L);
+  P.ka[0] = xc(1.0L / P.h, lo ? -P.w : 0.0L);
+  P.ka[n - 1] = xc(1.0L / P.h, hi ? -P.w : 0.0L);
+  P.ma[0] = P.ma[n - 1] = 2.0L * P.h / 6.0L;
+  P.kb = -1.0L / P.h;
+  P.mb = P.h / 6.0L;
+  return P;
 }
 
-void apply_mass(const Pencil& P, const std::vector<cd>& x, std::vector<cd>& y) {
+// x^T K x without cancellation: K = (1/h) sum over elements of (e_i - e_{i+1})
+// (e_i - e_{i+1})^T minus i*w on the absorbing corners.
+xc stiff_form(const XPencil& P, const std::vector<xc>& x) {
+  xc s = 0.0L;
+  for (int i = 0; i + 1 < P.n; ++i) {
+    const xc d = x[i + 1] - x[i];
+    s += d * d;
+  }
+  s /= P.h;
+  if (P.lo) s -= xc(0.0L, P.w) * x[0] * x[0];
+  if (P.hi) s -= xc(0.0L, P.w) * x[P.n - 1] * x[P.n - 1];
+  return s;
+}
+
+// x^T M x = (h/6) sum over elements of (2 x_i^2 + 2 x_i x_{i+1} + 2 x_{i+1}^2).
+xc mass_form(const XPencil& P, const std::vector<xc>& x) {
+  xc s = 0.0L;
+  for (int i = 0; i + 1 < P.n; ++i) s += x[i] * x[i] + x[i] * x[i + 1] + x[i + 1] * x[i + 1];
+  return s * (P.h / 3.0L);
+}
+
+void apply_mass(const XPencil& P, const std::vector<xc>& x, std::vector<xc>& y) {
   for (int i = 0; i < P.n; ++i) {
-    cd v = P.ma[i] * x[i];
+    xc v = P.ma[i] * x[i];
     if (i > 0) v += P.mb * x[i - 1];
     if (i + 1 < P.n) v += P.mb * x[i + 1];
     y[i] = v;
@@ -131,45 +180,48 @@ void apply_mass(const Pencil& P, const std::vector<cd>& x, std::vector<cd>& y) {
 
 // One eigenpair from an approximate eigenvalue: inverse iteration steps with
 // the Rayleigh-quotient shift.  Returns the refined eigenvalue, the boundary
-// entries of the M-normalised eigenvector and the relative eigen-residual.
+// entries of the M-normalised eigenvector and the normwise backward error.
 struct Refined {
   cd lam, v0, v1;
   double resid;
 };
 
-Refined refine(const Pencil& P, cd lam, int steps) {
+Refined refine(const XPencil& P, cd lam0, int steps) {
   const int n = P.n;
-  std::vector<cd> x(n), y(n), dl(n), d(n), du(n), b(n);
+  std::vector<xc> x(n), y(n), dl(n), d(n), du(n), b(n);
   // Deterministic start vector with components of both parities.
-  for (int i = 0; i < n; ++i) x[i] = 1.7 + std::cos(0.913 * i + 0.3);
+  for (int i = 0; i < n; ++i) x[i] = 1.7L + std::cos(0.913L * i + 0.3L);
   // bound of ||K||_inf: interior rows sum to 4/h, corner rows |k|/h + 1/h
-  const double knorm = 4.0 * std::abs(P.kb) + std::abs(P.ka[0]) + std::abs(P.ka[n - 1]);
+  const xr knorm = 4.0L * std::abs(P.kb) + std::abs(P.ka[0]) + std::abs(P.ka[n - 1]);
+  xc lam(lam0.real(), lam0.imag());
   for (int s = 0; s < steps; ++s) {
     for (int i = 0; i < n; ++i) {
       d[i] = P.ka[i] - lam * P.ma[i];
       if (i + 1 < n) dl[i] = du[i] = P.kb - lam * P.mb;
     }
     apply_mass(P, x, b);
-    tri_solve_pp(dl, d, du, b, y, 1e-300 + 1e-30 * knorm);
-    double nrm = 0.0;
+    tri_solve_pp(dl, d, du, b, y, 1e-4000L + 1e-60L * knorm);
+    xr nrm = 0.0L;
     for (int i = 0; i < n; ++i) nrm = std::max(nrm, std::abs(y[i]));
     for (int i = 0; i < n; ++i) x[i] = y[i] / nrm;
-    lam = quad_form(P, x, true) / quad_form(P, x, false);
+    lam = stiff_form(P, x) / mass_form(P, x);
   }
-  const cd s = std::sqrt(quad_form(P, x, false));
-  for (int i = 0; i < n; ++i) x[i] /= s;
+  const xc sc = std::sqrt(mass_form(P, x));
+  for (int i = 0; i < n; ++i) x[i] /= sc;
   // normwise backward error ||(K - lam M) x|| / ((||K|| + |lam| ||M||) ||x||), max norms
-  double rnum = 0.0, xmax = 0.0;
+  xr rnum = 0.0L, xmax = 0.0L;
   for (int i = 0; i < n; ++i) {
-    cd kx = P.ka[i] * x[i], mx = P.ma[i] * x[i];
+    xc kx = P.ka[i] * x[i], mx = P.ma[i] * x[i];
     if (i > 0) { kx += P.kb * x[i - 1]; mx += P.mb * x[i - 1]; }
     if (i + 1 < n) { kx += P.kb * x[i + 1]; mx += P.mb * x[i + 1]; }
     rnum = std::max(rnum, std::abs(kx - lam * mx));
     xmax = std::max(xmax, std::abs(x[i]));
   }
-  const double mnorm = 6.0 * P.mb;  // ||M||_inf = h
-  const double rden = (knorm + std::abs(lam) * mnorm) * xmax;
-  return Refined{lam, x[0], x[n - 1], rden > 0 ? rnum / rden : 0.0};
+  const xr mnorm = 6.0L * P.mb;  // ||M||_inf = h
+  const xr rden = (knorm + std::abs(lam) * mnorm) * xmax;
+  return Refined{cd((double)lam.real(), (double)lam.imag()), cd((double)x[0].real(), (double)x[0].imag()),
+                 cd((double)x[n - 1].real(), (double)x[n - 1].imag()),
+                 rden > 0 ? (double)(rnum / rden) : 0.0};
 }
 
 }  // namespace
@@ -224,11 +276,12 @@ int eig1d(int n, double h, double omega, int lo, int hi, std::vector<cd>& lam_ou
       if (!std::isfinite(lam[j].real()) || !std::isfinite(lam[j].imag())) return HELM_ENOCONV;
   }
   // Refinement: 3 inverse-iteration steps with Rayleigh-quotient shifts.
+  const XPencil XP = make_xpencil(n, h, omega, lo, hi);
   std::vector<Refined> R(n);
   double worst = 0.0;
 #pragma omp parallel for schedule(dynamic, 16) reduction(max : worst)
   for (int j = 0; j < n; ++j) {
-    R[j] = refine(P, lam[j], 3);
+    R[j] = refine(XP, lam[j], 3);
     worst = std::max(worst, R[j].resid);
   }
   if (!(worst < 1e-12)) return HELM_ENOCONV;

@@ -97,6 +97,22 @@ struct helm_plan {
   helm::DevMem W0, W1, W2, R, part, VB, PIb, P0, P1, P2, P3, scratch, norms;
   std::vector<double> h_norms;
   helm_report rep{};
+  // per-kernel event timing
+  struct Ev {
+    hipEvent_t a, b;
+    int cls;
+    double bytes;
+  };
+  bool prof = false;
+  std::vector<Ev> evs;
+  size_t nev = 0;
+  helm_kernel_stats kst{};
+  ~helm_plan() {
+    for (auto& e : evs) {
+      (void)hipEventDestroy(e.a);
+      (void)hipEventDestroy(e.b);
+    }
+  }
 };
 
 namespace helm {
@@ -118,6 +134,48 @@ int map_err(hipError_t e) {
     hipError_t _e = (expr);             \
     if (_e != hipSuccess) return map_err(_e); \
   } while (0)
+
+// Kernel slots of helm_kernel_stats.
+enum KSlot { K_FFT64 = 0, K_FFT32 = 1, K_LINES = 2, K_INNER_MID = 3, K_SUM = 4, K_OUTER_MID = 5, K_RESID = 6 };
+
+// Launch through `fn` (returning hipError_t), bracketed by events if profiling.
+template <class F> hipError_t timed(helm_plan* p, int cls, double bytes, hipStream_t st, F&& fn) {
+  if (!p->prof) return fn();
+  if (p->nev == p->evs.size()) {
+    helm_plan::Ev e;
+    hipError_t r = hipEventCreate(&e.a);
+    if (r != hipSuccess) return r;
+    r = hipEventCreate(&e.b);
+    if (r != hipSuccess) return r;
+    p->evs.push_back(e);
+  }
+  helm_plan::Ev& e = p->evs[p->nev++];
+  e.cls = cls;
+  e.bytes = bytes;
+  hipError_t r = hipEventRecord(e.a, st);
+  if (r != hipSuccess) return r;
+  r = fn();
+  if (r != hipSuccess) return r;
+  return hipEventRecord(e.b, st);
+}
+
+hipError_t collect_events(helm_plan* p) {
+  for (size_t i = 0; i < p->nev; ++i) {
+    helm_plan::Ev& e = p->evs[i];
+    hipError_t r = hipEventSynchronize(e.b);
+    if (r != hipSuccess) return r;
+    float ms = 0.f;
+    r = hipEventElapsedTime(&ms, e.a, e.b);
+    if (r != hipSuccess) return r;
+    p->kst.ms[e.cls] += ms;
+    p->kst.bytes[e.cls] += e.bytes;
+    p->kst.calls[e.cls] += 1;
+  }
+  p->nev = 0;
+  return hipSuccess;
+}
+
+size_t esz_of(int kind) { return kind == ST_C64 ? sizeof(float2) : sizeof(double2); }
 
 Roots* get_roots(helm_plan* p, int L, int sign) {
   auto& mp = sign < 0 ? p->roots_fwd : p->roots_inv;
@@ -185,7 +243,8 @@ int run_fft(helm_plan* p, const PAxis& a, int sign, bool fp32, const void* in, i
     f.scale = scale;
     f.scale_c = scale_c;
     f.tw = fp32 ? r->f.p : r->d.p;
-    HCHK(launch_fft_pass(f, fp32, in, out, st));
+    const double by = (double)O * n * S * (esz_of(in_kind) + esz_of(out_kind));
+    HCHK(timed(p, fp32 ? K_FFT32 : K_FFT64, by, st, [&] { return launch_fft_pass(f, fp32, in, out, st); }));
     return HELM_OK;
   }
   // four-step: n = na * nb, x = a + na b, k = c + nb d
@@ -212,7 +271,8 @@ int run_fft(helm_plan* p, const PAxis& a, int sign, bool fp32, const void* in, i
   f1.sign = sign;
   f1.tw = fp32 ? r1->f.p : r1->d.p;
   f1.tw4 = fp32 ? rn->f.p : rn->d.p;
-  HCHK(launch_fft_pass(f1, fp32, in, tmp, st));
+  const double by1 = (double)O * n * S * (esz_of(in_kind) + esz_of(tmp_kind));
+  HCHK(timed(p, fp32 ? K_FFT32 : K_FFT64, by1, st, [&] { return launch_fft_pass(f1, fp32, in, tmp, st); }));
   FftPass f2;
   f2.L = na;
   radix_plan(na, f2);
@@ -232,7 +292,8 @@ int run_fft(helm_plan* p, const PAxis& a, int sign, bool fp32, const void* in, i
   f2.scale = scale;
   f2.scale_c = scale_c;
   f2.tw = fp32 ? r2->f.p : r2->d.p;
-  HCHK(launch_fft_pass(f2, fp32, tmp, out, st));
+  const double by2 = (double)O * n * S * (esz_of(tmp_kind) + esz_of(out_kind));
+  HCHK(timed(p, fp32 ? K_FFT32 : K_FFT64, by2, st, [&] { return launch_fft_pass(f2, fp32, tmp, out, st); }));
   return HELM_OK;
 }
 
@@ -298,6 +359,7 @@ int inner_solve(helm_plan* p, const Level& lv, const InnerIO& io, hipStream_t st
   base.kLo = p->kLo;
   base.kHi = p->kHi;
   double2* part = p->part.as<double2>();
+  const double elems = (double)lv.nb * lv.nO * lv.nI * lv.nL;
   int tile, nt;
   tiles_for(1, lv.nb, lv.nO, lv.nI, lv.nL, &tile, &nt);
 
@@ -315,7 +377,7 @@ int inner_solve(helm_plan* p, const Level& lv, const InnerIO& io, hipStream_t st
   s1.part = part;
   s1.tile = tile;
   s1.ntiles = nt;
-  HCHK(launch_lines(s1, st));
+  HCHK(timed(p, K_LINES, io.in ? elems * esz_of(io.in_kind) : 0.0, st, [&] { return launch_lines(s1, st); }));
 
   InnerMidArgs m;
   m.nb = lv.nb;
@@ -332,7 +394,8 @@ int inner_solve(helm_plan* p, const Level& lv, const InnerIO& io, hipStream_t st
   m.hL = p->hL;
   m.kLo = p->kLo;
   m.kHi = p->kHi;
-  HCHK(launch_inner_mid(m, st));
+  HCHK(timed(p, K_INNER_MID, (double)lv.nb * lv.nO * 2 * lv.nL * sizeof(double2) * (nt + 2), st,
+             [&] { return launch_inner_mid(m, st); }));
 
   // S2: partial solution with the absorbing-boundary eigenvectors.
   LineArgs s2 = base;
@@ -346,11 +409,12 @@ int inner_solve(helm_plan* p, const Level& lv, const InnerIO& io, hipStream_t st
   s2.part = part;
   s2.tile = tile;
   s2.ntiles = nt;
-  HCHK(launch_lines(s2, st));
+  HCHK(timed(p, K_LINES, 0.0, st, [&] { return launch_lines(s2, st); }));
 
   m.vb_in = p->VB.as<double2>();
   m.vb_out = nullptr;
-  HCHK(launch_inner_mid(m, st));
+  HCHK(timed(p, K_INNER_MID, (double)lv.nb * lv.nO * 2 * lv.nL * sizeof(double2) * (nt + 2), st,
+             [&] { return launch_inner_mid(m, st); }));
 
   // S3: corrected periodic solve.
   LineArgs s3 = base;
@@ -380,7 +444,8 @@ int inner_solve(helm_plan* p, const Level& lv, const InnerIO& io, hipStream_t st
     s3.tile = tl;
     s3.ntiles = ntl;
   }
-  HCHK(launch_lines(s3, st));
+  const double by3 = (io.in ? elems * esz_of(io.in_kind) : 0.0) + (io.out ? elems * esz_of(io.out_kind) : 0.0);
+  HCHK(timed(p, K_LINES, by3, st, [&] { return launch_lines(s3, st); }));
   return HELM_OK;
 }
 
@@ -404,9 +469,11 @@ int sum_to_planes(helm_plan* p, const Level& lv, double2* out, hipStream_t st) {
   int tl, ntl;
   tiles_for(2, lv.nb, lv.nO, lv.nI, lv.nL, &tl, &ntl);
   const int64_t total = (int64_t)lv.nb * 2 * lv.nI * lv.nL;
-  hipLaunchKernelGGL(sum_to_planes_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st,
-                     p->part.as<double2>(), lv.nb, lv.nI, lv.nL, ntl, out);
-  HCHK(hipGetLastError());
+  HCHK(timed(p, K_SUM, (double)total * sizeof(double2) * (ntl + 1), st, [&] {
+    hipLaunchKernelGGL(sum_to_planes_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st,
+                       p->part.as<double2>(), lv.nb, lv.nI, lv.nL, ntl, out);
+    return hipGetLastError();
+  }));
   return HELM_OK;
 }
 
@@ -482,7 +549,7 @@ int solve_once(helm_plan* p, const void* x, int x_kind, double2* u, int accumula
     om.k2Hi = make_double2(1.0, A2.hi ? -p->omega * A2.h : 0.0);
     om.k3Lo = p->kLo;
     om.k3Hi = p->kHi;
-    HCHK(launch_outer_mid(om, st));
+    HCHK(timed(p, K_OUTER_MID, (double)nb * 2 * plane * sizeof(double2) * 3, st, [&] { return launch_outer_mid(om, st); }));
     rc = run_fft(p, A2, -1, false, Wp, ST_C128, Rh, ST_C128, (int64_t)nb * 2, n3, A2.invmu, 1.0, 0, Vh,
                  ST_C128, st);
     if (rc) return rc;
@@ -504,7 +571,7 @@ int solve_once(helm_plan* p, const void* x, int x_kind, double2* u, int accumula
     om.a = Vp;
     om.c = Wp;
     om.r = Vh;
-    HCHK(launch_outer_mid(om, st));
+    HCHK(timed(p, K_OUTER_MID, (double)nb * 2 * plane * sizeof(double2) * 3, st, [&] { return launch_outer_mid(om, st); }));
     rc = run_fft(p, A2, -1, false, Vh, ST_C128, Rh, ST_C128, (int64_t)nb * 2, n3, A2.invmu, 1.0, 0, Wp,
                  ST_C128, st);
     if (rc) return rc;
@@ -598,7 +665,8 @@ int residual_norms(helm_plan* p, const double2* u, const double2* f, void* r, in
   a.f = f;
   a.r = r;
   a.r_kind = r_kind;
-  HCHK(launch_residual(a, st));
+  HCHK(timed(p, K_RESID, (double)npoints(p) * nb * (2 * sizeof(double2) + (r ? esz_of(r_kind) : 0)), st,
+             [&] { return launch_residual(a, st); }));
   HCHK(hipMemcpyAsync(p->h_norms.data(), a.norms, nb * 2 * sizeof(double), hipMemcpyDeviceToHost, st));
   HCHK(hipStreamSynchronize(st));
   double mx = 0.0;
@@ -822,6 +890,28 @@ int helm_residual(helm_plan* p, const void* u, const void* f, void* r, double* r
                                 ST_C128, nrhs, st, &mx, &rel);
   for (int b = 0; b < nrhs; ++b) rel_res[b] = rc == HELM_OK ? rel[b] : NAN;
   return rc;
+}
+
+int helm_profile(helm_plan* p, int on) {
+  if (!p) return HELM_EINVAL;
+  p->prof = on != 0;
+  return HELM_OK;
+}
+
+int helm_kernel_stats_get(helm_plan* p, helm_kernel_stats* out, int reset) {
+  if (!p || !out) return HELM_EINVAL;
+  const hipError_t e = collect_events(p);
+  if (e != hipSuccess) return map_err(e);
+  *out = p->kst;
+  if (reset) p->kst = helm_kernel_stats{};
+  return HELM_OK;
+}
+
+const char* helm_kernel_name(int k) {
+  static const char* names[HELM_NKERNELS] = {
+      "fft_pass_kernel<double2>", "fft_pass_kernel<float2>", "lines_kernel", "inner_mid_kernel",
+      "sum_to_planes_kernel",     "outer_mid_kernel",        "residual_kernel", nullptr};
+  return (k >= 0 && k < HELM_NKERNELS) ? names[k] : nullptr;
 }
 
 void helm_destroy(helm_plan* p) {

@@ -30,7 +30,10 @@ PREC_MIXED = 1
 EXPORTS = (
     "helm_default_options", "helm_setup", "helm_solve", "helm_report_get",
     "helm_residual", "helm_destroy", "helm_strerror", "helm_eig1d",
+    "helm_profile", "helm_kernel_stats_get", "helm_kernel_name",
 )
+
+NKERNELS = 8
 
 
 class Options(ctypes.Structure):
@@ -43,6 +46,11 @@ class Report(ctypes.Structure):
                 ("precision", ctypes.c_int), ("nrhs", ctypes.c_int),
                 ("rel_residual_max", ctypes.c_double),
                 ("rel_residual_first", ctypes.c_double)]
+
+
+class KernelStats(ctypes.Structure):
+    _fields_ = [("ms", ctypes.c_double * 8), ("bytes", ctypes.c_double * 8),
+                ("calls", ctypes.c_int * 8)]
 
 
 class HelmError(RuntimeError):
@@ -81,6 +89,12 @@ def lib():
     L.helm_eig1d.argtypes = [ctypes.c_int64, ctypes.c_double, ctypes.c_double, ctypes.c_int,
                              ctypes.c_int, dp, dp]
     L.helm_eig1d.restype = ctypes.c_int
+    L.helm_profile.argtypes = [vp, ctypes.c_int]
+    L.helm_profile.restype = ctypes.c_int
+    L.helm_kernel_stats_get.argtypes = [vp, ctypes.POINTER(KernelStats), ctypes.c_int]
+    L.helm_kernel_stats_get.restype = ctypes.c_int
+    L.helm_kernel_name.argtypes = [ctypes.c_int]
+    L.helm_kernel_name.restype = ctypes.c_char_p
     _lib = L
     return L
 
@@ -190,6 +204,26 @@ class Plan:
         if rc != HELM_OK:
             raise HelmError(rc, "helm_residual")
         return rel
+
+    def profile(self, on=True):
+        """Time every kernel launch of later solves with HIP events."""
+        rc = lib().helm_profile(self._p, int(bool(on)))
+        if rc != HELM_OK:
+            raise HelmError(rc, "helm_profile")
+
+    def kernel_stats(self, reset=True):
+        """{kernel name: {"ms", "bytes", "calls"}} accumulated since the last reset."""
+        st = KernelStats()
+        rc = lib().helm_kernel_stats_get(self._p, ctypes.byref(st), int(bool(reset)))
+        if rc != HELM_OK:
+            raise HelmError(rc, "helm_kernel_stats_get")
+        out = {}
+        for k in range(NKERNELS):
+            name = lib().helm_kernel_name(k)
+            if name is None or st.calls[k] == 0:
+                continue
+            out[name.decode()] = {"ms": st.ms[k], "bytes": st.bytes[k], "calls": st.calls[k]}
+        return out
 
     def close(self):
         if getattr(self, "_p", None):
