@@ -32,28 +32,52 @@ __global__ __launch_bounds__(kMidThreads) void sum_partials_kernel(const double2
   out[i] = s;
 }
 
-// One block per (group, x-tile); LDS holds v over the tile plus a halo of 1.
+// One block per (group, 30 columns): 8 tile slices x 32 columns (the 30
+// outputs plus a halo of one on each side) sum the partials in parallel, the
+// slices are combined in LDS in a fixed order, then the 2x2 block operator is
+// applied.
+constexpr int kMidCols = 32;
+constexpr int kMidSlices = kMidThreads / kMidCols;
+constexpr int kMidOut = kMidCols - 2;
+
 __global__ __launch_bounds__(kMidThreads) void inner_mid_kernel(InnerMidArgs a) {
-  __shared__ double2 v[2][kMidThreads + 2];
-  const int ntx = (a.nL + kMidThreads - 1) / kMidThreads;
-  const int64_t g = blockIdx.x / ntx;
-  const int x0 = (int)(blockIdx.x % ntx) * kMidThreads;
+  __shared__ double2 sl[kMidSlices][2][kMidCols];
+  __shared__ double2 v[2][kMidCols];
   const int nL = a.nL;
+  const int ntx = (nL + kMidOut - 1) / kMidOut;
+  const int64_t g = blockIdx.x / ntx;
+  const int x0 = (int)(blockIdx.x % ntx) * kMidOut;
   const int64_t per = 2 * (int64_t)nL;
-  for (int s = threadIdx.x; s < kMidThreads + 2; s += kMidThreads) {
-    const int x = x0 - 1 + s;
-    for (int k = 0; k < 2; ++k) {
-      double2 acc = make_double2(0, 0);
-      if (x >= 0 && x < nL) {
-        const double2* p = a.part + g * a.ntiles * per + k * nL + x;
-        for (int t = 0; t < a.ntiles; ++t) acc = cadd(acc, p[t * per]);
-        if (a.vb_out) a.vb_out[g * per + k * nL + x] = acc;
-        if (a.vb_in) acc = cadd(acc, a.vb_in[g * per + k * nL + x]);
+  {
+    const int xi = threadIdx.x % kMidCols, ts = threadIdx.x / kMidCols;
+    const int x = x0 - 1 + xi;
+    double2 s0 = make_double2(0, 0), s1 = make_double2(0, 0);
+    if (x >= 0 && x < nL) {
+      const double2* p = a.part + g * a.ntiles * per + x;
+      for (int t = ts; t < a.ntiles; t += kMidSlices) {
+        s0 = cadd(s0, p[t * per]);
+        s1 = cadd(s1, p[t * per + nL]);
       }
-      v[k][s] = acc;
     }
+    sl[ts][0][xi] = s0;
+    sl[ts][1][xi] = s1;
   }
   __syncthreads();
+  if (threadIdx.x < 2 * kMidCols) {
+    const int k = threadIdx.x / kMidCols, xi = threadIdx.x % kMidCols;
+    const int x = x0 - 1 + xi;
+    double2 acc = make_double2(0, 0);
+    for (int ts = 0; ts < kMidSlices; ++ts) acc = cadd(acc, sl[ts][k][xi]);
+    if (x >= 0 && x < nL) {
+      if (a.vb_out && xi >= 1 && xi <= kMidOut) a.vb_out[g * per + k * nL + x] = acc;
+      if (a.vb_in) acc = cadd(acc, a.vb_in[g * per + k * nL + x]);
+    } else {
+      acc = make_double2(0, 0);
+    }
+    v[k][xi] = acc;
+  }
+  __syncthreads();
+  if (threadIdx.x >= kMidOut) return;
   const int x = x0 + threadIdx.x;
   if (x >= nL) return;
   const int64_t l = g % a.nO;
@@ -139,7 +163,7 @@ hipError_t launch_sum_partials(const double2* part, int ngroups, int ntiles, int
 }
 
 hipError_t launch_inner_mid(const InnerMidArgs& a, hipStream_t s) {
-  const int ntx = (a.nL + kMidThreads - 1) / kMidThreads;
+  const int ntx = (a.nL + kMidOut - 1) / kMidOut;
   const int64_t blocks = (int64_t)a.nb * a.nO * ntx;
   if (blocks <= 0) return hipSuccess;
   hipLaunchKernelGGL(inner_mid_kernel, dim3((unsigned)blocks), dim3(kMidThreads), 0, s, a);

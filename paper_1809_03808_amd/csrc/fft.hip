@@ -126,10 +126,8 @@ template <> __device__ inline void dft<8, double2>(double2* v, int sign) { dft8(
 template <> __device__ inline void dft<8, float2>(float2* v, int sign) { dft8(v, sign); }
 
 struct PassDev {
-  int L, W, nst, sign, acc, in_kind, out_kind;
-  int radix[8];
+  int sign, acc, in_kind, out_kind;
   int64_t I, od, in_so, in_sj, out_so1, out_so2, out_sk, tw4_S;
-  int tw4_n;
   int64_t ntile;  // tiles along I
   double scale_c;
   const void* tw;
@@ -137,32 +135,47 @@ struct PassDev {
   const double* scale;
 };
 
-// One Stockham stage: X (L points per column) -> Y.  Each thread owns the
-// butterflies t = tid + q*NT, t -> (j = t / W, w = t % W).  All reads of the
-// stage happen before the barrier, all writes after it, so X and Y may be
-// the same LDS buffer.
-template <int R, int VMAX, typename C>
-__device__ inline void run_stage(const PassDev& p, int Ns, bool first, bool last, C* sm,
-                                 const void* in, void* out, int64_t o, int64_t i0) {
-  constexpr int NB = VMAX / R;  // butterflies per thread (upper bound)
-  const int L = p.L, W = p.W;
-  const int LR = L / R;
-  const int nbf = LR * W;
+// Compile-time Stockham plan of a power-of-two length L: one radix-2 or -4
+// stage first when log2(L) is not a multiple of 3, then radix-8 stages.
+constexpr int ilog2(int L) { return L <= 1 ? 0 : 1 + ilog2(L / 2); }
+constexpr int nstages(int L) { return ilog2(L) / 3 + (ilog2(L) % 3 ? 1 : 0); }
+constexpr int radix_of(int L, int s) {
+  return (ilog2(L) % 3 && s == 0) ? (ilog2(L) % 3 == 1 ? 2 : 4) : 8;
+}
+// Columns per tile: a 64 KB LDS tile of L x W complex values, W <= 64.
+template <typename C> constexpr int tile_w(int L) {
+  return (65536 / (L * (int)sizeof(C))) < 64 ? 65536 / (L * (int)sizeof(C)) : 64;
+}
+
+// One Stockham stage of radix R with Ns points already combined.  Thread
+// tid owns butterflies t = tid + q*NT, t -> (j = t / W, w = t % W); since W
+// divides NT, w = tid % W for every q.  All reads of a stage precede the
+// barrier and all writes follow it, so the stage works in place in LDS.  The
+// first stage reads global memory, the last writes it (with the four-step
+// twiddle, the per-mode scale and the optional accumulation).
+template <int L, int W, int R, int Ns, bool FIRST, bool LAST, typename C>
+__device__ inline void stage(const PassDev& p, C* sm, const void* in, void* out, int64_t o, int64_t i0,
+                             int64_t oq, int64_t orr, int64_t a4) {
+  constexpr int LR = L / R;
+  constexpr int NBF = LR * W;
+  constexpr int NB = (NBF + kFftThreads - 1) / kFftThreads;
   const int tid = threadIdx.x;
+  const int w = tid % W;
+  const int64_t col = i0 + w;
+  const bool colok = col < p.I;
   const C* tw = reinterpret_cast<const C*>(p.tw);
   C v[NB][R];
 #pragma unroll
   for (int q = 0; q < NB; ++q) {
     const int t = tid + q * kFftThreads;
-    if (t < nbf) {
-      const int w = t % W, j = t / W;
+    if (NB * kFftThreads == NBF || t < NBF) {
+      const int j = t / W;
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         const int row = j + r * LR;
-        if (first) {
-          const int64_t col = i0 + w;
+        if constexpr (FIRST) {
           C x;
-          if (col < p.I) x = load_as<C>(in, o * p.in_so + (int64_t)row * p.in_sj + col, p.in_kind);
+          if (colok) x = load_as<C>(in, o * p.in_so + (int64_t)row * p.in_sj + col, p.in_kind);
           else { x.x = 0; x.y = 0; }
           v[q][r] = x;
         } else {
@@ -171,77 +184,103 @@ __device__ inline void run_stage(const PassDev& p, int Ns, bool first, bool last
       }
     }
   }
-  if (!first) __syncthreads();
+  if constexpr (!FIRST) __syncthreads();
 #pragma unroll
   for (int q = 0; q < NB; ++q) {
     const int t = tid + q * kFftThreads;
-    if (t < nbf) {
-      const int w = t % W, j = t / W;
+    if (NB * kFftThreads == NBF || t < NBF) {
+      const int j = t / W;
       const int k = j % Ns;
-      if (Ns > 1) {
-        const int step = L / (Ns * R);
+      if constexpr (Ns > 1) {
+        constexpr int step = L / (Ns * R);
 #pragma unroll
         for (int r = 1; r < R; ++r) v[q][r] = cmul(v[q][r], tw[r * k * step]);
       }
       dft<R, C>(v[q], p.sign);
       const int base = (j / Ns) * Ns * R + k;
-      if (!last) {
+      if constexpr (!LAST) {
 #pragma unroll
         for (int r = 0; r < R; ++r) sm[(base + r * Ns) * W + w] = v[q][r];
       } else {
-        const int64_t col = i0 + w;
-        if (col < p.I) {
-          const int64_t oq = o / p.od, orr = o % p.od;
+        if (colok) {
 #pragma unroll
           for (int r = 0; r < R; ++r) {
-            const int64_t kk = base + r * Ns;  // output frequency of this pass
+            const int kk = base + r * Ns;  // output frequency of this pass
             C y = v[q][r];
             if (p.tw4) {
+              // kk < L and a4 < n / L, so kk * a4 < n: no reduction needed
               const C* t4 = reinterpret_cast<const C*>(p.tw4);
-              y = cmul(y, t4[(kk * (col / p.tw4_S)) % p.tw4_n]);
+              y = cmul(y, t4[kk * a4]);
             }
             double s = p.scale_c;
             if (p.scale) s *= p.scale[orr + p.od * kk];
             y.x = (typename RealOf<C>::T)(y.x * s);
             y.y = (typename RealOf<C>::T)(y.y * s);
-            store_as<C>(out, oq * p.out_so1 + orr * p.out_so2 + kk * p.out_sk + col, p.out_kind, y,
-                        p.acc);
+            store_as<C>(out, oq * p.out_so1 + orr * p.out_so2 + kk * p.out_sk + col, p.out_kind, y, p.acc);
           }
         }
       }
     }
   }
-  if (!last) __syncthreads();
+  if constexpr (!LAST) __syncthreads();
+}
+
+template <int L, int W, int S, int Ns, typename C>
+__device__ inline void stages(const PassDev& p, C* sm, const void* in, void* out, int64_t o, int64_t i0,
+                              int64_t oq, int64_t orr, int64_t a4) {
+  if constexpr (S < nstages(L)) {
+    constexpr int R = radix_of(L, S);
+    stage<L, W, R, Ns, S == 0, S == nstages(L) - 1, C>(p, sm, in, out, o, i0, oq, orr, a4);
+    stages<L, W, S + 1, Ns * R, C>(p, sm, in, out, o, i0, oq, orr, a4);
+  }
+}
+
+template <int L, typename C>
+__global__ __launch_bounds__(kFftThreads) void fft_pass_kernel(PassDev p, const void* in, void* out) {
+  constexpr int W = tile_w<C>(L);
+  __shared__ C sm[nstages(L) > 1 ? L * W : 1];
+  const int64_t blk = blockIdx.x;
+  const int64_t o = blk / p.ntile;
+  const int64_t i0 = (blk - o * p.ntile) * W;
+  const int64_t oq = o / p.od, orr = o - oq * p.od;
+  const int64_t a4 = p.tw4 ? (i0 + (int64_t)(threadIdx.x % W)) / p.tw4_S : 0;
+  stages<L, W, 0, 1, C>(p, sm, in, out, o, i0, oq, orr, a4);
+}
+
+template <int L, typename C>
+hipError_t launch_L(const PassDev& p, int64_t O, const void* in, void* out, hipStream_t s) {
+  constexpr int W = tile_w<C>(L);
+  PassDev q = p;
+  q.ntile = (p.I + W - 1) / W;
+  const int64_t blocks = O * q.ntile;
+  if (blocks <= 0) return hipSuccess;
+  if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((fft_pass_kernel<L, C>), dim3((unsigned)blocks), dim3(kFftThreads), 0, s, q, in, out);
+  return hipGetLastError();
 }
 
 template <typename C>
-__global__ __launch_bounds__(kFftThreads) void fft_pass_kernel(PassDev p, const void* in, void* out) {
-  extern __shared__ unsigned char smem_raw[];
-  C* sm = reinterpret_cast<C*>(smem_raw);
-  constexpr int VMAX = kFftLdsBytes / (int)sizeof(C) / kFftThreads;
-  const int64_t blk = blockIdx.x;
-  const int64_t o = blk / p.ntile;
-  const int64_t i0 = (blk % p.ntile) * p.W;
-  int Ns = 1;
-  for (int st = 0; st < p.nst; ++st) {
-    const bool first = st == 0, last = st == p.nst - 1;
-    switch (p.radix[st]) {
-      case 8: run_stage<8, VMAX, C>(p, Ns, first, last, sm, in, out, o, i0); break;
-      case 4: run_stage<4, VMAX, C>(p, Ns, first, last, sm, in, out, o, i0); break;
-      default: run_stage<2, VMAX, C>(p, Ns, first, last, sm, in, out, o, i0); break;
-    }
-    Ns *= p.radix[st];
+hipError_t launch_typed(int L, const PassDev& p, int64_t O, const void* in, void* out, hipStream_t s) {
+  switch (L) {
+    case 2: return launch_L<2, C>(p, O, in, out, s);
+    case 4: return launch_L<4, C>(p, O, in, out, s);
+    case 8: return launch_L<8, C>(p, O, in, out, s);
+    case 16: return launch_L<16, C>(p, O, in, out, s);
+    case 32: return launch_L<32, C>(p, O, in, out, s);
+    case 64: return launch_L<64, C>(p, O, in, out, s);
+    case 128: return launch_L<128, C>(p, O, in, out, s);
+    case 256: return launch_L<256, C>(p, O, in, out, s);
+    case 512: return launch_L<512, C>(p, O, in, out, s);
+    default: return hipErrorInvalidValue;
   }
 }
 
 }  // namespace
 
+int fft_tile_width(int L, bool fp32) { return fp32 ? tile_w<float2>(L) : tile_w<double2>(L); }
+
 hipError_t launch_fft_pass(const FftPass& f, bool fp32, const void* in, void* out, hipStream_t s) {
   PassDev p;
-  p.L = f.L;
-  p.W = f.W;
-  p.nst = f.nst;
-  for (int i = 0; i < 8; ++i) p.radix[i] = f.radix[i];
   p.I = f.I;
   p.od = f.od;
   p.in_so = f.in_so;
@@ -250,7 +289,6 @@ hipError_t launch_fft_pass(const FftPass& f, bool fp32, const void* in, void* ou
   p.out_so2 = f.out_so2;
   p.out_sk = f.out_sk;
   p.tw4_S = f.tw4_S;
-  p.tw4_n = f.tw4_n;
   p.acc = f.accumulate;
   p.in_kind = f.in_kind;
   p.out_kind = f.out_kind;
@@ -259,19 +297,9 @@ hipError_t launch_fft_pass(const FftPass& f, bool fp32, const void* in, void* ou
   p.tw4 = f.tw4;
   p.scale = f.scale;
   p.sign = f.sign;
-  p.ntile = (f.I + f.W - 1) / f.W;
-  const size_t esz = fp32 ? sizeof(float2) : sizeof(double2);
-  const size_t lds = (size_t)f.L * f.W * esz;
-  if (f.L < 2 || f.W < 1 || lds > (size_t)kFftLdsBytes || (int64_t)f.L * f.W > (int64_t)kFftLdsBytes / (int64_t)esz)
-    return hipErrorInvalidValue;
-  const int64_t blocks = f.O * p.ntile;
-  if (blocks <= 0) return hipSuccess;
-  if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
-  if (fp32)
-    hipLaunchKernelGGL(fft_pass_kernel<float2>, dim3((unsigned)blocks), dim3(kFftThreads), lds, s, p, in, out);
-  else
-    hipLaunchKernelGGL(fft_pass_kernel<double2>, dim3((unsigned)blocks), dim3(kFftThreads), lds, s, p, in, out);
-  return hipGetLastError();
+  p.ntile = 0;
+  if (f.tw4 && f.tw4_S <= 0) return hipErrorInvalidValue;
+  return fp32 ? launch_typed<float2>(f.L, p, f.O, in, out, s) : launch_typed<double2>(f.L, p, f.O, in, out, s);
 }
 
 }  // namespace helm

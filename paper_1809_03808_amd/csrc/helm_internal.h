@@ -39,6 +39,20 @@ __device__ inline double2 crcp(double2 a) {
   const double d = 1.0 / (a.x * a.x + a.y * a.y);
   return make_double2(a.x * d, -a.y * d);
 }
+// 1/d for a normal positive double: hardware reciprocal estimate refined by
+// two Newton-Raphson steps r <- r + r (1 - d r) (each doubles the number of
+// correct bits), about 1 ulp; cheaper than the IEEE division sequence.
+__device__ inline double rcp_nr(double d) {
+  double r = __builtin_amdgcn_rcp(d);
+  double e = fma(-d, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-d, r, 1.0);
+  return fma(r, e, r);
+}
+__device__ inline double2 crcp_fast(double2 a) {
+  const double d = rcp_nr(a.x * a.x + a.y * a.y);
+  return make_double2(a.x * d, -a.y * d);
+}
 __device__ inline double2 to_d2(double2 a) { return a; }
 __device__ inline double2 to_d2(float2 a) { return make_double2((double)a.x, (double)a.y); }
 template <typename C> __device__ inline C from_d2(double2 a);
@@ -79,6 +93,8 @@ struct FftPass {
   const double* scale = nullptr;
 };
 
+// Inner columns per tile of a length-L pass (fixed per length and precision).
+int fft_tile_width(int L, bool fp32);
 // Launch one pass.  `fp32` selects float arithmetic (tables in float).
 hipError_t launch_fft_pass(const FftPass& p, bool fp32, const void* in, void* out,
                            hipStream_t s);
@@ -117,13 +133,18 @@ struct LineArgs {
   const double2* rho0 = nullptr;
   const double2* rho1 = nullptr;
   double2* part = nullptr;
+  const double2* piv = nullptr;  // [nO*nI][nL] reciprocal pivots of the line matrices
   int tile = 0;    // lines per workgroup tile
   int ntiles = 0;  // tiles along the reduced (or flattened) index
 };
 
 hipError_t launch_lines(LineArgs a, hipStream_t s);
-// Number of partial planes per reduction group for a given tile request.
-int lines_tile(const LineArgs& a, int reduce_extent, int target_blocks);
+// Lanes per line P, rows per lane c and block size NT for a line length.
+void lines_geometry(int nL, int* P, int* c, int* NT);
+// Factor table of the line matrices (l, m), l < nO, m < nI, of `a` (sO, sI,
+// sC and the line axis are used): piv[(l nI + m) nL + x] = 1/p_x, the
+// reciprocal Thomas pivots.  Computed once per plan.
+hipError_t launch_line_factors(const LineArgs& a, double2* piv, hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // Boundary kernels (boundary.hip)

@@ -95,6 +95,11 @@ struct helm_plan {
   int cap_rhs = 0;
   int cap_prec = -1;
   helm::DevMem W0, W1, W2, R, part, VB, PIb, P0, P1, P2, P3, scratch, norms;
+  // LU factor tables (reciprocal Thomas pivots) per line-matrix family
+  // (outer branch, inner branch): [0] = (B, B), [1] = (B, A), [2] = (A, B),
+  // [3] = (A, A); 2D uses [0], [1].
+  helm::DevMem factors;
+  const double2* seed[4] = {nullptr, nullptr, nullptr, nullptr};
   std::vector<double> h_norms;
   helm_report rep{};
   // per-kernel event timing
@@ -207,13 +212,7 @@ void radix_plan(int L, FftPass& f) {
   for (int i = 0; i < p / 3; ++i) f.radix[f.nst++] = 8;
 }
 
-int pick_W(int L, int64_t I, bool fp32) {
-  const int esz = fp32 ? 8 : 16;
-  int W = 1;
-  while (W < 64 && (int64_t)(2 * W) * L * esz <= 64 * 1024) W *= 2;
-  while (W > 1 && W / 2 >= I) W /= 2;
-  return W;
-}
+int pick_W(int L, int64_t, bool fp32) { return fft_tile_width(L, fp32); }
 
 // DFT along a periodised axis of data [O][n][S] (S contiguous).
 // Forward: sign -1 and per-mode scale 1/mu (if scale), inverse: sign +1, 1/n.
@@ -297,18 +296,17 @@ int run_fft(helm_plan* p, const PAxis& a, int sign, bool fp32, const void* in, i
   return HELM_OK;
 }
 
-// Lines per tile: at least 16 lines feed each partial sum (partials stay
-// below 1/8 of an N-sized array) and enough tiles to fill the chip.
+// Lines per tile: at least 8 lines feed each partial sum (partials stay
+// below 1/4 of an N-sized array) and enough tiles to fill the chip.
 void tiles_for(int red, int nb, int nO, int nI, int nL, int* tile, int* ntiles) {
-  int P = 1;
-  while (P * 8 < nL) P <<= 1;
-  const int NT = P > 256 ? P : 256;
+  int P, c, NT;
+  lines_geometry(nL, &P, &c, &NT);
   const int LPB = NT / P;
   const int64_t extent = red == 1 ? nI : (red == 2 ? nO : (int64_t)nb * nO * nI);
   const int64_t groups = red == 1 ? (int64_t)nb * nO : (red == 2 ? (int64_t)nb * nI : 1);
-  int64_t t = red ? 16 : LPB;
+  int64_t t = red ? 8 : LPB;
   const int64_t lines = extent * groups;
-  const int64_t target = 4096;
+  const int64_t target = 2048;
   if (lines / t > target) t = (lines + target - 1) / target;
   if (red && t > extent) t = extent;
   t = (t + LPB - 1) / LPB * LPB;
@@ -343,6 +341,8 @@ struct InnerIO {
   int out_kind = ST_C128;
   const double2* rhoL0 = nullptr;
   const double2* rhoL1 = nullptr;
+  const double2* seedB = nullptr;  // line matrices with the periodic inner branch (S1, S3)
+  const double2* seedA = nullptr;  // line matrices with the absorbing inner branch (S2)
 };
 
 int inner_solve(helm_plan* p, const Level& lv, const InnerIO& io, hipStream_t st) {
@@ -358,6 +358,7 @@ int inner_solve(helm_plan* p, const Level& lv, const InnerIO& io, hipStream_t st
   base.hL = p->hL;
   base.kLo = p->kLo;
   base.kHi = p->kHi;
+  base.piv = io.seedB;
   double2* part = p->part.as<double2>();
   const double elems = (double)lv.nb * lv.nO * lv.nI * lv.nL;
   int tile, nt;
@@ -400,6 +401,7 @@ int inner_solve(helm_plan* p, const Level& lv, const InnerIO& io, hipStream_t st
   // S2: partial solution with the absorbing-boundary eigenvectors.
   LineArgs s2 = base;
   s2.sI = I.sigA;
+  s2.piv = io.seedA;
   s2.PI = p->PIb.as<double2>();
   s2.beta0 = I.va0d;
   s2.beta1 = I.va1d;
@@ -495,6 +497,8 @@ int solve_once(helm_plan* p, const void* x, int x_kind, double2* u, int accumula
     io.in_kind = T;
     io.out = W0;
     io.out_kind = T;
+    io.seedB = p->seed[0];
+    io.seedA = p->seed[1];
     rc = inner_solve(p, lv, io, st);
     if (rc) return rc;
     return run_fft(p, A1, +1, fp32, W0, T, u, ST_C128, nb, n2, nullptr, 1.0 / n1, accumulate, W1, T, st);
@@ -520,6 +524,8 @@ int solve_once(helm_plan* p, const void* x, int x_kind, double2* u, int accumula
   {
     InnerIO io;
     io.sO = A1.sigB;
+    io.seedB = p->seed[0];
+    io.seedA = p->seed[1];
     io.in = W0;
     io.in_kind = T;
     io.rhoL0 = A1.redB0;
@@ -555,6 +561,8 @@ int solve_once(helm_plan* p, const void* x, int x_kind, double2* u, int accumula
     if (rc) return rc;
     InnerIO io;
     io.sO = A1.sigA;
+    io.seedB = p->seed[2];
+    io.seedA = p->seed[3];
     io.PO = Rh;
     io.alpha0 = A1.va0d;
     io.alpha1 = A1.va1d;
@@ -580,6 +588,8 @@ int solve_once(helm_plan* p, const void* x, int x_kind, double2* u, int accumula
   {
     InnerIO io;
     io.sO = A1.sigB;
+    io.seedB = p->seed[0];
+    io.seedA = p->seed[1];
     io.in = W0;
     io.in_kind = T;
     io.PO = Rh;
@@ -815,6 +825,34 @@ int helm_setup(int dim, const int64_t* grid, const double* h, double omega, uint
     a.va0d = t + 6 * a.n;
     a.va1d = t + 7 * a.n;
     a.invmu = reinterpret_cast<double*>((char*)a.tab.p + nb2);
+  }
+  // LU factors (reciprocal Thomas pivots) of every line-matrix family: sigma
+  // depends on the outer and inner branches only (Section 4.1.2 computes the
+  // LU decompositions of H_B and H_A at initialisation).
+  {
+    const int nO = dim == 2 ? 1 : p->ax[0].n;
+    const int nI = p->ax[dim - 2].n;
+    const int fam = dim == 2 ? 2 : 4;
+    const size_t per = (size_t)nO * nI * p->nL;
+    if (p->factors.ensure(per * fam * sizeof(double2)) != hipSuccess) return HELM_ENOMEM;
+    for (int k = 0; k < fam; ++k) {
+      LineArgs la;
+      la.nb = 1;
+      la.nO = nO;
+      la.nI = nI;
+      la.nL = p->nL;
+      la.sC = make_double2(-omega * omega, 0.0);
+      la.hL = p->hL;
+      la.kLo = p->kLo;
+      la.kHi = p->kHi;
+      const PAxis& inner = p->ax[dim - 2];
+      la.sI = (k & 1) ? inner.sigA : inner.sigB;
+      la.sO = dim == 2 ? nullptr : ((k & 2) ? p->ax[0].sigA : p->ax[0].sigB);
+      double2* dst = p->factors.as<double2>() + per * k;
+      if (launch_line_factors(la, dst, nullptr) != hipSuccess) return HELM_EDEVICE;
+      p->seed[k] = dst;
+    }
+    if (hipDeviceSynchronize() != hipSuccess) return HELM_EDEVICE;
   }
   p->rep.status = HELM_OK;
   p->rep.rel_residual_max = -1;
