@@ -70,9 +70,9 @@ def _traffic(kernel, workload, calls_per_step):
 
 
 def cpu_baseline():
-    """The oracle (banded LU, zgbsv, complex128) on a 512 x 512 sample of the
+    """The oracle (banded LU, zgbsv, complex128) on a 720 x 720 sample of the
     same problem family: 10 points per wavelength, absorbing on all faces,
-    one Gaussian right-hand side."""
+    one Gaussian right-hand side (10-30 s of host work)."""
     import numpy as np
     from oracle import fem
     from paper_1809_03808_amd import inputs
@@ -81,7 +81,7 @@ def cpu_baseline():
         cores = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
     except Exception:
         cores = 1
-    n = 512
+    n = 720
     grid = (n, n)
     h = inputs.spacing(grid)
     w = inputs.omega_for_ppw(n, 10.0)
@@ -94,7 +94,7 @@ def cpu_baseline():
     del u
     return {"value": n * n / dt, "unit": "unknowns/s", "cores": int(cores), "kind": "oracle",
             "seconds": dt, "rel_residual": res,
-            "sample": "2D 512x512 nodes, 10 points/wavelength, absorbing faces, 1 Gaussian RHS; "
+            "sample": "2D 720x720 nodes, 10 points/wavelength, absorbing faces, 1 Gaussian RHS; "
                       "banded LU (LAPACK zgbsv via scipy) in complex128 -- the 4096x4096 case "
                       "itself would need ~3.3 TB for the band"}
 
