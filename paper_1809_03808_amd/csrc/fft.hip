@@ -127,6 +127,8 @@ template <> __device__ inline void dft<8, float2>(float2* v, int sign) { dft8(v,
 
 struct PassDev {
   int sign, acc, in_kind, out_kind;
+  const void* cmode;
+  const int* skip;
   int64_t I, od, in_so, in_sj, out_so1, out_so2, out_sk, tw4_S;
   int64_t ntile;  // tiles along I
   double scale_c;
@@ -212,6 +214,7 @@ __device__ inline void stage(const PassDev& p, C* sm, const void* in, void* out,
               const C* t4 = reinterpret_cast<const C*>(p.tw4);
               y = cmul(y, t4[kk * a4]);
             }
+            if (p.cmode) y = cmul(y, reinterpret_cast<const C*>(p.cmode)[orr + p.od * kk]);
             double s = p.scale_c;
             if (p.scale) s *= p.scale[orr + p.od * kk];
             y.x = (typename RealOf<C>::T)(y.x * s);
@@ -239,6 +242,7 @@ template <int L, typename C>
 __global__ __launch_bounds__(kFftThreads) void fft_pass_kernel(PassDev p, const void* in, void* out) {
   constexpr int W = tile_w<C>(L);
   __shared__ C sm[nstages(L) > 1 ? L * W : 1];
+  if (p.skip && *p.skip) return;
   const int64_t blk = blockIdx.x;
   const int64_t o = blk / p.ntile;
   const int64_t i0 = (blk - o * p.ntile) * W;
@@ -275,7 +279,43 @@ hipError_t launch_typed(int L, const PassDev& p, int64_t O, const void* in, void
   }
 }
 
+template <typename C>
+__global__ __launch_bounds__(256) void chirp_kernel(ChirpArgs a, const void* in, void* out, int64_t nib) {
+  if (a.skip && *a.skip) return;
+  const int64_t o = blockIdx.y;
+  const int64_t k = blockIdx.x / nib;
+  const int64_t i = (blockIdx.x - k * nib) * 256 + threadIdx.x;
+  if (i >= a.S) return;
+  const C w = reinterpret_cast<const C*>(a.w)[k < a.n ? k : 0];
+  if (!a.post) {
+    C v;
+    if (k < a.n) v = cmul(load_as<C>(in, (o * a.n + k) * a.S + i, a.in_kind), w);
+    else { v.x = 0; v.y = 0; }
+    store_as<C>(out, (o * a.M + k) * a.S + i, a.out_kind, v, 0);
+  } else {
+    C v = cmul(load_as<C>(in, (o * a.M + k) * a.S + i, a.in_kind), w);
+    double s = a.scale_c;
+    if (a.scale) s *= a.scale[k];
+    v.x = (typename RealOf<C>::T)(v.x * s);
+    v.y = (typename RealOf<C>::T)(v.y * s);
+    store_as<C>(out, (o * a.n + k) * a.S + i, a.out_kind, v, a.accumulate);
+  }
+}
+
 }  // namespace
+
+hipError_t launch_chirp(const ChirpArgs& a, bool fp32, const void* in, void* out, hipStream_t s) {
+  const int64_t K = a.post ? a.n : a.M;
+  const int64_t nib = (a.S + 255) / 256;
+  if (a.O <= 0 || K <= 0 || a.S <= 0) return hipSuccess;
+  if (a.O > 65535 || K * nib > 0x7fffffffLL) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)(K * nib), (unsigned)a.O);
+  if (fp32)
+    hipLaunchKernelGGL(chirp_kernel<float2>, grid, dim3(256), 0, s, a, in, out, nib);
+  else
+    hipLaunchKernelGGL(chirp_kernel<double2>, grid, dim3(256), 0, s, a, in, out, nib);
+  return hipGetLastError();
+}
 
 int fft_tile_width(int L, bool fp32) { return fp32 ? tile_w<float2>(L) : tile_w<double2>(L); }
 
@@ -297,6 +337,8 @@ hipError_t launch_fft_pass(const FftPass& f, bool fp32, const void* in, void* ou
   p.tw4 = f.tw4;
   p.scale = f.scale;
   p.sign = f.sign;
+  p.cmode = f.cmode;
+  p.skip = f.skip;
   p.ntile = 0;
   if (f.tw4 && f.tw4_S <= 0) return hipErrorInvalidValue;
   return fp32 ? launch_typed<float2>(f.L, p, f.O, in, out, s) : launch_typed<double2>(f.L, p, f.O, in, out, s);

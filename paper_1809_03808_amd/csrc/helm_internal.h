@@ -91,6 +91,8 @@ struct FftPass {
   const void* tw = nullptr;    // L roots e^{sign 2 pi i t / L}
   const void* tw4 = nullptr;   // tw4_n roots
   const double* scale = nullptr;
+  const void* cmode = nullptr;  // optional complex per-mode multiplier (compute precision)
+  const int* skip = nullptr;    // device flag: when non-zero the pass does nothing
 };
 
 // Inner columns per tile of a length-L pass (fixed per length and precision).
@@ -98,6 +100,23 @@ int fft_tile_width(int L, bool fp32);
 // Launch one pass.  `fp32` selects float arithmetic (tables in float).
 hipError_t launch_fft_pass(const FftPass& p, bool fp32, const void* in, void* out,
                            hipStream_t s);
+
+// Chirp step of Bluestein's algorithm for a length-n DFT along the axis of
+// [O][n][S] data, with a power-of-two convolution length M >= 2n - 1:
+//   pre  (post = 0): t[o][j][i] = x[o][j][i] w[j] for j < n, 0 for n <= j < M
+//   post (post = 1): y[o][k][i] (+)= w[k] t[o][k][i] scale[k] scale_c, k < n
+// w[j] = e^{sign pi i j^2 / n} (table, compute precision).
+struct ChirpArgs {
+  int post = 0;
+  int64_t O = 0, n = 0, M = 0, S = 0;
+  int in_kind = ST_C128, out_kind = ST_C128;
+  const void* w = nullptr;
+  const double* scale = nullptr;
+  double scale_c = 1.0;
+  int accumulate = 0;
+  const int* skip = nullptr;
+};
+hipError_t launch_chirp(const ChirpArgs& a, bool fp32, const void* in, void* out, hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // Batched tridiagonal line solves (lines.hip)

@@ -70,6 +70,14 @@ struct PAxis {
   double* invmu = nullptr;
   BDiff bd;
   int na = 0, nbp = 0;  // FFT split n = na * nbp (nbp = first pass length); na = 1 -> one pass
+  // Bluestein (chirp-z) transform for lengths that are not powers of two:
+  // convolution length M (power of two >= 2n - 1) split as Mna * Mnbp.
+  int blue = 0, M = 0, Mna = 0, Mnbp = 0;
+  DevMem btab;
+  const void* chirp_d[2] = {nullptr, nullptr};  // w for sign -1, +1 (double2[n])
+  const void* chirp_f[2] = {nullptr, nullptr};  // same in float2
+  const void* bhat_d[2] = {nullptr, nullptr};   // FFT_M of the convolution kernel (double2[M])
+  const void* bhat_f[2] = {nullptr, nullptr};
 };
 
 }  // namespace
@@ -94,7 +102,7 @@ struct helm_plan {
   // workspace
   int cap_rhs = 0;
   int cap_prec = -1;
-  helm::DevMem W0, W1, W2, R, part, VB, PIb, P0, P1, P2, P3, scratch, norms;
+  helm::DevMem W0, W1, W2, R, part, VB, PIb, P0, P1, P2, P3, scratch, norms, BT1, BT2;
   // LU factor tables (reciprocal Thomas pivots) per line-matrix family
   // (outer branch, inner branch): [0] = (B, B), [1] = (B, A), [2] = (A, B),
   // [3] = (A, A); 2D uses [0], [1].
@@ -182,6 +190,84 @@ hipError_t collect_events(helm_plan* p) {
 
 size_t esz_of(int kind) { return kind == ST_C64 ? sizeof(float2) : sizeof(double2); }
 
+// In-place radix-2 DFT of a power-of-two length on the host (FP64), sign -1
+// forward; used once per plan for the transformed Bluestein kernel.
+void host_fft(std::vector<cd>& x, int sign) {
+  const int n = (int)x.size();
+  for (int i = 1, j = 0; i < n; ++i) {
+    int bit = n >> 1;
+    for (; j & bit; bit >>= 1) j ^= bit;
+    j ^= bit;
+    if (i < j) std::swap(x[i], x[j]);
+  }
+  for (int len = 2; len <= n; len <<= 1) {
+    for (int k = 0; k < len / 2; ++k) {
+      const double th = sign * 2.0 * M_PI * k / len;
+      const cd w(std::cos(th), std::sin(th));
+      for (int i = 0; i < n; i += len) {
+        const cd u = x[i + k], v = x[i + k + len / 2] * w;
+        x[i + k] = u + v;
+        x[i + k + len / 2] = u - v;
+      }
+    }
+  }
+}
+
+void pow2_split(int L, int* na, int* nb) {
+  if (L <= 512) {
+    *na = 1;
+    *nb = L;
+    return;
+  }
+  int b = 1;
+  while ((int64_t)b * b < L) b <<= 1;
+  *nb = b;
+  *na = L / b;
+}
+
+// Bluestein tables of a periodised axis of length n (not a power of two):
+// chirp w_s[j] = e^{s pi i (j^2 mod 2n)/n} and the length-M forward DFT of the
+// kernel b_s[m] = e^{-s pi i m^2/n} (m in (-n, n), wrapped modulo M), s = -1, +1.
+int setup_bluestein(PAxis& a) {
+  const int n = a.n;
+  int M = 1;
+  while (M < 2 * n - 1) M <<= 1;
+  if (M > 512 * 512) return HELM_EUNSUPPORTED;
+  a.blue = 1;
+  a.M = M;
+  pow2_split(M, &a.Mna, &a.Mnbp);
+  std::vector<double2> hd((size_t)2 * n + 2 * M);
+  std::vector<float2> hf((size_t)2 * n + 2 * M);
+  for (int si = 0; si < 2; ++si) {
+    const int sg = si == 0 ? -1 : 1;
+    std::vector<cd> b(M, cd(0.0));
+    for (int64_t j = 0; j < n; ++j) {
+      const int64_t jj = (j * j) % (2 * (int64_t)n);
+      const double th = M_PI * (double)jj / n;
+      const cd w(std::cos(th), sg * std::sin(th));
+      hd[(size_t)si * n + j] = hd2(w);
+      b[j] = std::conj(w);
+      if (j > 0) b[M - j] = std::conj(w);
+    }
+    host_fft(b, -1);
+    for (int k = 0; k < M; ++k) hd[(size_t)2 * n + (size_t)si * M + k] = hd2(b[k]);
+  }
+  for (size_t i = 0; i < hd.size(); ++i) hf[i] = make_float2((float)hd[i].x, (float)hd[i].y);
+  const size_t bd = hd.size() * sizeof(double2), bf = hf.size() * sizeof(float2);
+  if (a.btab.ensure(bd + bf) != hipSuccess) return HELM_ENOMEM;
+  if (upload(a.btab.p, hd.data(), bd) != hipSuccess) return HELM_EDEVICE;
+  if (upload((char*)a.btab.p + bd, hf.data(), bf) != hipSuccess) return HELM_EDEVICE;
+  const double2* d = a.btab.as<double2>();
+  const float2* f = reinterpret_cast<const float2*>((char*)a.btab.p + bd);
+  for (int si = 0; si < 2; ++si) {
+    a.chirp_d[si] = d + (size_t)si * n;
+    a.bhat_d[si] = d + 2 * (size_t)n + (size_t)si * M;
+    a.chirp_f[si] = f + (size_t)si * n;
+    a.bhat_f[si] = f + 2 * (size_t)n + (size_t)si * M;
+  }
+  return HELM_OK;
+}
+
 Roots* get_roots(helm_plan* p, int L, int sign) {
   auto& mp = sign < 0 ? p->roots_fwd : p->roots_inv;
   auto it = mp.find(L);
@@ -214,43 +300,44 @@ void radix_plan(int L, FftPass& f) {
 
 int pick_W(int L, int64_t, bool fp32) { return fft_tile_width(L, fp32); }
 
-// DFT along a periodised axis of data [O][n][S] (S contiguous).
-// Forward: sign -1 and per-mode scale 1/mu (if scale), inverse: sign +1, 1/n.
-int run_fft(helm_plan* p, const PAxis& a, int sign, bool fp32, const void* in, int in_kind, void* out,
-            int out_kind, int64_t O, int64_t S, const double* scale, double scale_c, int accumulate,
-            void* tmp, int tmp_kind, hipStream_t st) {
-  const int n = a.n;
-  if (a.na <= 1) {
-    Roots* r = get_roots(p, n, sign);
+// Power-of-two DFT of length L along the axis of [O][L][S] data (S
+// contiguous): one pass for L <= 512, else the four-step split L = na * nb
+// (pass 1 writes `tmp`).  Per-mode complex multiplier `cmode`, real `scale`.
+int run_pow2(helm_plan* p, int L, int na, int nb, int sign, bool fp32, const void* in, int in_kind, void* out,
+             int out_kind, int64_t O, int64_t S, const double* scale, double scale_c, const void* cmode,
+             int accumulate, void* tmp, int tmp_kind, const int* skip, hipStream_t st) {
+  if (na <= 1) {
+    Roots* r = get_roots(p, L, sign);
     if (!r) return HELM_ENOMEM;
     FftPass f;
-    f.L = n;
-    radix_plan(n, f);
+    f.L = L;
+    radix_plan(L, f);
     f.I = S;
     f.O = O;
     f.od = 1;
-    f.in_so = (int64_t)n * S;
+    f.in_so = (int64_t)L * S;
     f.in_sj = S;
-    f.out_so1 = (int64_t)n * S;
+    f.out_so1 = (int64_t)L * S;
     f.out_so2 = 0;
     f.out_sk = S;
-    f.W = pick_W(n, S, fp32);
+    f.W = pick_W(L, S, fp32);
     f.in_kind = in_kind;
     f.out_kind = out_kind;
     f.accumulate = accumulate;
     f.sign = sign;
     f.scale = scale;
     f.scale_c = scale_c;
+    f.cmode = cmode;
+    f.skip = skip;
     f.tw = fp32 ? r->f.p : r->d.p;
-    const double by = (double)O * n * S * (esz_of(in_kind) + esz_of(out_kind));
+    const double by = (double)O * L * S * (esz_of(in_kind) + esz_of(out_kind));
     HCHK(timed(p, fp32 ? K_FFT32 : K_FFT64, by, st, [&] { return launch_fft_pass(f, fp32, in, out, st); }));
     return HELM_OK;
   }
-  // four-step: n = na * nb, x = a + na b, k = c + nb d
-  const int na = a.na, nb = a.nbp;
+  // four-step: L = na * nb, x = a + na b, k = c + nb d
   Roots* r1 = get_roots(p, nb, sign);
   Roots* r2 = get_roots(p, na, sign);
-  Roots* rn = get_roots(p, n, sign);
+  Roots* rn = get_roots(p, L, sign);
   if (!r1 || !r2 || !rn) return HELM_ENOMEM;
   FftPass f1;
   f1.L = nb;
@@ -258,19 +345,20 @@ int run_fft(helm_plan* p, const PAxis& a, int sign, bool fp32, const void* in, i
   f1.I = (int64_t)na * S;
   f1.O = O;
   f1.od = 1;
-  f1.in_so = (int64_t)n * S;
+  f1.in_so = (int64_t)L * S;
   f1.in_sj = (int64_t)na * S;
-  f1.out_so1 = (int64_t)n * S;
+  f1.out_so1 = (int64_t)L * S;
   f1.out_sk = (int64_t)na * S;
   f1.tw4_S = S;
-  f1.tw4_n = n;
+  f1.tw4_n = L;
   f1.W = pick_W(nb, f1.I, fp32);
   f1.in_kind = in_kind;
   f1.out_kind = tmp_kind;
   f1.sign = sign;
+  f1.skip = skip;
   f1.tw = fp32 ? r1->f.p : r1->d.p;
   f1.tw4 = fp32 ? rn->f.p : rn->d.p;
-  const double by1 = (double)O * n * S * (esz_of(in_kind) + esz_of(tmp_kind));
+  const double by1 = (double)O * L * S * (esz_of(in_kind) + esz_of(tmp_kind));
   HCHK(timed(p, fp32 ? K_FFT32 : K_FFT64, by1, st, [&] { return launch_fft_pass(f1, fp32, in, tmp, st); }));
   FftPass f2;
   f2.L = na;
@@ -280,7 +368,7 @@ int run_fft(helm_plan* p, const PAxis& a, int sign, bool fp32, const void* in, i
   f2.od = nb;
   f2.in_so = (int64_t)na * S;
   f2.in_sj = S;
-  f2.out_so1 = (int64_t)n * S;
+  f2.out_so1 = (int64_t)L * S;
   f2.out_so2 = S;
   f2.out_sk = (int64_t)nb * S;
   f2.W = pick_W(na, S, fp32);
@@ -290,9 +378,56 @@ int run_fft(helm_plan* p, const PAxis& a, int sign, bool fp32, const void* in, i
   f2.sign = sign;
   f2.scale = scale;
   f2.scale_c = scale_c;
+  f2.cmode = cmode;
+  f2.skip = skip;
   f2.tw = fp32 ? r2->f.p : r2->d.p;
-  const double by2 = (double)O * n * S * (esz_of(tmp_kind) + esz_of(out_kind));
+  const double by2 = (double)O * L * S * (esz_of(tmp_kind) + esz_of(out_kind));
   HCHK(timed(p, fp32 ? K_FFT32 : K_FFT64, by2, st, [&] { return launch_fft_pass(f2, fp32, tmp, out, st); }));
+  return HELM_OK;
+}
+
+// DFT along a periodised axis of data [O][n][S] (S contiguous).
+// Forward: sign -1 and per-mode scale 1/mu (if scale), inverse: sign +1, 1/n.
+// Lengths that are not powers of two use Bluestein's chirp-z algorithm:
+// jk = (j^2 + k^2 - (k - j)^2)/2 turns the DFT into a convolution, evaluated
+// with power-of-two transforms of length M >= 2n - 1 in the plan's BT1/BT2.
+int run_fft(helm_plan* p, const PAxis& a, int sign, bool fp32, const void* in, int in_kind, void* out,
+            int out_kind, int64_t O, int64_t S, const double* scale, double scale_c, int accumulate,
+            void* tmp, int tmp_kind, hipStream_t st, const int* skip = nullptr) {
+  if (!a.blue)
+    return run_pow2(p, a.n, a.na, a.nbp, sign, fp32, in, in_kind, out, out_kind, O, S, scale, scale_c,
+                    nullptr, accumulate, tmp, tmp_kind, skip, st);
+  const int si = sign < 0 ? 0 : 1;
+  const int T = fp32 ? ST_C64 : ST_C128;
+  void* t1 = p->BT1.p;
+  void* t2 = p->BT2.p;
+  ChirpArgs c;
+  c.O = O;
+  c.n = a.n;
+  c.M = a.M;
+  c.S = S;
+  c.w = fp32 ? a.chirp_f[si] : a.chirp_d[si];
+  c.skip = skip;
+  c.post = 0;
+  c.in_kind = in_kind;
+  c.out_kind = T;
+  const double byc = (double)O * S * ((double)a.n * esz_of(in_kind) + (double)a.M * esz_of(T));
+  HCHK(timed(p, fp32 ? K_FFT32 : K_FFT64, byc, st, [&] { return launch_chirp(c, fp32, in, t1, st); }));
+  int rc = run_pow2(p, a.M, a.Mna, a.Mnbp, -1, fp32, t1, T, t1, T, O, S, nullptr, 1.0,
+                    fp32 ? a.bhat_f[si] : a.bhat_d[si], 0, t2, T, skip, st);
+  if (rc) return rc;
+  rc = run_pow2(p, a.M, a.Mna, a.Mnbp, +1, fp32, t1, T, t1, T, O, S, nullptr, 1.0, nullptr, 0, t2, T, skip, st);
+  if (rc) return rc;
+  c.post = 1;
+  c.in_kind = T;
+  c.out_kind = out_kind;
+  c.scale = scale;
+  c.scale_c = scale_c / a.M;
+  c.accumulate = accumulate;
+  const double byp = (double)O * S * ((double)a.M * esz_of(T) + (double)a.n * esz_of(out_kind) * (accumulate ? 2 : 1));
+  HCHK(timed(p, fp32 ? K_FFT32 : K_FFT64, byp, st, [&] { return launch_chirp(c, fp32, t1, out, st); }));
+  (void)tmp;
+  (void)tmp_kind;
   return HELM_OK;
 }
 
@@ -641,6 +776,21 @@ int ensure_workspace(helm_plan* p, int nb, bool fp32, bool need_r) {
     HCHK(p->P2.ensure(pl));
     HCHK(p->P3.ensure(pl));
   }
+  // Bluestein temporaries: the largest [O][M][S] of any transform that uses them
+  {
+    size_t tmax = 0;
+    if (p->dim == 2) {
+      if (p->ax[0].blue) tmax = (size_t)nb * p->ax[0].M * p->nL;
+    } else {
+      if (p->ax[0].blue) tmax = std::max(tmax, (size_t)nb * p->ax[0].M * p->ax[1].n * p->nL);
+      if (p->ax[1].blue)
+        tmax = std::max(tmax, (size_t)nb * std::max(p->ax[0].n, 2) * p->ax[1].M * p->nL);
+    }
+    if (tmax) {
+      HCHK(p->BT1.ensure(tmax * sizeof(double2)));
+      HCHK(p->BT2.ensure(tmax * sizeof(double2)));
+    }
+  }
   HCHK(p->scratch.ensure((size_t)residual_scratch_len(p->dim, p->grid, nb) * sizeof(double)));
   HCHK(p->norms.ensure((size_t)nb * 2 * sizeof(double)));
   p->h_norms.resize(2 * nb);
@@ -794,16 +944,12 @@ int helm_setup(int dim, const int64_t* grid, const double* h, double omega, uint
     a.h = h[j];
     a.lo = (abc >> (2 * j)) & 1;
     a.hi = (abc >> (2 * j + 1)) & 1;
-    if (!is_pow2(a.n)) return HELM_EUNSUPPORTED;
-    if (a.n <= 512) {
-      a.na = 1;
-      a.nbp = a.n;
-    } else {
-      int nb = 1;
-      while ((int64_t)nb * nb < a.n) nb <<= 1;
-      a.nbp = nb;
-      a.na = a.n / nb;
+    if (is_pow2(a.n)) {
+      pow2_split(a.n, &a.na, &a.nbp);
       if (a.na > 512 || a.nbp > 512) return HELM_EUNSUPPORTED;
+    } else {
+      const int bst = setup_bluestein(a);
+      if (bst != HELM_OK) return bst;
     }
     const int st = eig1d(a.n, a.h, omega, a.lo, a.hi, a.lamA, a.va0, a.va1);
     if (st != HELM_OK) return st;

@@ -54,6 +54,13 @@ CASES_2D = [
     ((32, 33), 20.0, 0b1100),   # x1 both Neumann
     ((64, 41), 30.0, 0b0110),   # mixed faces on both axes
     ((1024, 21), 400.0, 0b1111),  # two-pass transform along x1
+    # periodised lengths that are not powers of two (chirp-z transform)
+    ((33, 20), 15.0, 0b1111),
+    ((12, 9), 6.0, 0b1111),
+    ((257, 65), 80.0, 0b1111),
+    ((100, 31), 30.0, 0b1100),
+    ((1025, 17), 300.0, 0b1111),  # chirp length 4096: two-pass inner transforms
+    ((3, 7), 2.0, 0b1111),        # smallest periodised axis
 ]
 
 
@@ -91,6 +98,9 @@ CASES_3D = [
     ((16, 8, 13), 12.0, 0b111111),
     ((8, 16, 7), 10.0, 0b110111),  # x2 low face Neumann
     ((16, 16, 16), 15.0, 0b111111),
+    ((12, 10, 9), 8.0, 0b111111),   # both periodised axes not powers of two
+    ((8, 24, 7), 10.0, 0b111111),
+    ((20, 16, 11), 12.0, 0b110111),
 ]
 
 
@@ -105,7 +115,8 @@ def test_3d_fp64_matches_banded_lu(grid, omega, mask):
     assert np.max(err) <= 1e-9
 
 
-@pytest.mark.parametrize("grid,omega", [((64, 77), 35.0), ((16, 16, 13), 14.0), ((1024, 17), 300.0)])
+@pytest.mark.parametrize("grid,omega", [((64, 77), 35.0), ((16, 16, 13), 14.0), ((1024, 17), 300.0),
+                                         ((513, 33), 150.0), ((12, 20, 9), 12.0)])
 def test_mixed_precision_refines_to_1e10(grid, omega):
     mask = (1 << (2 * len(grid))) - 1
     f = inputs.gaussian_batch(grid, [31, 32, 33]).astype(np.complex128)
