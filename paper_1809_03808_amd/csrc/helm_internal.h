@@ -152,7 +152,7 @@ struct LineArgs {
   const double2* rho0 = nullptr;
   const double2* rho1 = nullptr;
   double2* part = nullptr;
-  const double2* piv = nullptr;  // [nO*nI][nL] reciprocal pivots of the line matrices
+  const double2* piv = nullptr;  // [nO*nI][P] reciprocal pivot entering each lane chunk
   int tile = 0;    // lines per workgroup tile
   int ntiles = 0;  // tiles along the reduced (or flattened) index
 };
@@ -161,8 +161,9 @@ hipError_t launch_lines(LineArgs a, hipStream_t s);
 // Lanes per line P, rows per lane c and block size NT for a line length.
 void lines_geometry(int nL, int* P, int* c, int* NT);
 // Factor table of the line matrices (l, m), l < nO, m < nI, of `a` (sO, sI,
-// sC and the line axis are used): piv[(l nI + m) nL + x] = 1/p_x, the
-// reciprocal Thomas pivots.  Computed once per plan.
+// sC and the line axis are used): piv[(l nI + m) P + q] = 1/p_{q c - 1}, the
+// reciprocal Thomas pivot entering the chunk of lane q (P, c from
+// lines_geometry; entry q = 0 is zero).  Computed once per plan.
 hipError_t launch_line_factors(const LineArgs& a, double2* piv, hipStream_t s);
 
 // ---------------------------------------------------------------------------

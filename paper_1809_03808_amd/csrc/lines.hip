@@ -25,10 +25,11 @@
 // Each lane composes its c rows, the scan supplies the state entering the
 // chunk, and the lane then re-runs its rows sequentially.  The pivot state
 // entering each chunk depends on sigma only, so it is computed once per plan
-// and, from it, the reciprocal pivot of every row: the LU factors of each line
-// matrix are computed when the plan is built (factor_kernel), as the paper
-// does at initialisation, and the solves run the two affine scans, with wave
-// shuffles inside a wave and one LDS exchange between the waves of a line.
+// (factor_kernel; the paper likewise factors the line matrices at
+// initialisation) and stored as one reciprocal pivot per lane chunk; a solve
+// regenerates the c pivots of its chunk from it (c divisions instead of c
+// table reads) and runs the two affine scans, with wave shuffles inside a
+// wave and one LDS exchange between the waves of a line.
 // Arithmetic is FP64 whatever the storage precision.
 //
 // Right-hand sides may be generated from boundary planes (the rank-2 terms of
@@ -160,8 +161,6 @@ __device__ inline Aff scan_bwd(Aff v, int q, Aff* wbuf) {
   return ex;
 }
 
-template <typename T> __device__ inline double2 ld(const T* p, int64_t i) { return to_d2(p[i]); }
-
 struct LineDev {
   int nb, nO, nI, nL, c, red, tile, ntiles, iters;
   const double2* sO;
@@ -171,7 +170,7 @@ struct LineDev {
   double2 kLo, kHi;
   const void* in;
   const double2 *alpha0, *alpha1, *PO, *beta0, *beta1, *PI, *rho0, *rho1;
-  const double2* piv;   // [nO*nI][nL]: 1/pivot of every row (factor table)
+  const double2* piv;   // [nO*nI][P]: reciprocal pivot entering the chunk of each lane
   void* out;
   double2* part;
 };
@@ -202,107 +201,170 @@ __device__ inline double2 diag_of(const RowCoef& r, int x, int nL) {
 // e(x) = coupling between rows x-1 and x
 __device__ inline bool has_e(int x, int nL) { return x > 0 && x < nL; }
 
+// Line index (b, l, m) of slot `sl` of tile t at iteration `it`; false past
+// the end of the tile's extent.  Line counts stay below 2^31 (checked at
+// launch), so 32-bit index arithmetic suffices.
+__device__ inline bool decode_line(const LineDev& a, uint32_t g, uint32_t t, int lpb, int it, int sl,
+                                   uint32_t& b, uint32_t& l, uint32_t& m) {
+  const uint32_t li = t * (uint32_t)a.tile + (uint32_t)(it * lpb + sl);
+  const uint32_t nO = a.nO, nI = a.nI;
+  bool valid;
+  if (a.red == 1) {        // g = b*nO + l, li = m
+    valid = li < nI;
+    b = g / nO;
+    l = g - b * nO;
+    m = li;
+  } else if (a.red == 2) { // g = b*nI + m, li = l
+    valid = li < nO;
+    b = g / nI;
+    m = g - b * nI;
+    l = li;
+  } else {                 // li = (b*nO + l)*nI + m
+    valid = li < (uint32_t)a.nb * nO * nI;
+    const uint32_t bl = li / nI;
+    m = li - bl * nI;
+    b = bl / nO;
+    l = bl - b * nO;
+  }
+  if (!valid) { b = 0; l = 0; m = 0; }
+  return valid;
+}
+
+// Padded position of element e of a wave's staging area: one pad slot per 8
+// elements, so that lanes reading rows lane*c + j (c = 8) hit distinct banks.
+__device__ inline int stage_pos(int e) { return e + (e >> 3); }
+
+// Memory layout and staging.  Line rows are contiguous in memory but lane q
+// owns the contiguous chunk [q c, q c + c), so direct per-lane loads would
+// touch 64 cache lines per wave instruction.  Instead every wave loads the
+// rows of its lanes with consecutive lanes on consecutive rows (whole cache
+// lines per instruction), assembles the right-hand side there, and passes the
+// chunks through its own LDS area (64 c padded complex values); solutions to
+// be stored take the same route back.  The per-wave area is only touched by
+// its own wave, whose LDS accesses execute in program order, except in the
+// final cross-slot reduction, which is fenced by block barriers.
 template <typename TIN, typename TOUT, int NT, int P, bool RED>
 __global__ __launch_bounds__(NT) void lines_kernel(LineDev a) {
-  __shared__ Aff wbuf[NT / 64 + 1];
-  // Reduction accumulators, lane-major: accs[(k c + j) NT + tid] holds the
-  // weighted sum (weight k) of row q c + j of this thread's lines.
-  extern __shared__ double2 accs[];
+  constexpr int NW = NT / 64;
+  constexpr int PW = P < 64 ? P : 64;     // lanes of one line inside a wave
+  constexpr int SPW = 64 / PW;            // lines per wave
+  constexpr int LPB = NT / P;             // lines per block
+  __shared__ Aff wbuf[NW + 1];
+  extern __shared__ double2 stage[];  // NW areas of AREA = 72 c padded values
 
-  constexpr int LPB = NT / P;
   const int c = a.c, nL = a.nL;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int slot = tid / P, q = tid - slot * P;
   const int x0 = q * c;
+  const int wslot0 = (wv * 64) / P;                   // first line slot of this wave
+  const int wx0 = (P >= 64 ? (wv * 64) % P : 0) * c;  // first row this wave stages
+  const int seg = PW * c;                             // rows of one line staged by this wave
+  const int AREA = 72 * c;
+  double2* S = stage + wv * AREA;
 
-  const int64_t blk = blockIdx.x;
-  int64_t g = 0, t = 0;
+  const uint32_t blk = blockIdx.x;
+  uint32_t g = 0, t = 0;
   if (a.red) {
-    g = blk / a.ntiles;
-    t = blk - g * a.ntiles;
+    g = blk / (uint32_t)a.ntiles;
+    t = blk - g * (uint32_t)a.ntiles;
   } else {
     t = blk;
   }
 
+  double2 acc0[kCMax], acc1[kCMax];
   if constexpr (RED) {
-    for (int j = 0; j < 2 * c; ++j) accs[j * NT + tid] = make_double2(0, 0);
+#pragma unroll
+    for (int j = 0; j < kCMax; ++j) acc0[j] = acc1[j] = make_double2(0, 0);
   }
 
-  // Line handled by this slot at iteration `it`.
-  auto decode = [&](int it, int64_t& b, int64_t& l, int64_t& m) -> bool {
-    const int64_t li = t * a.tile + (int64_t)it * LPB + slot;
-    bool valid;
-    if (a.red == 1) {        // g = b*nO + l, li = m
-      valid = li < a.nI;
-      b = g / a.nO;
-      l = g - b * a.nO;
-      m = li;
-    } else if (a.red == 2) { // g = b*nI + m, li = l
-      valid = li < a.nO;
-      b = g / a.nI;
-      m = g - b * a.nI;
-      l = li;
-    } else {                 // li = (b*nO + l)*nI + m
-      valid = li < (int64_t)a.nb * a.nO * a.nI;
-      m = li % a.nI;
-      const int64_t bl = li / a.nI;
-      l = bl % a.nO;
-      b = bl / a.nO;
-    }
-    if (!valid) { b = 0; l = 0; m = 0; }
-    return valid;
-  };
   for (int it = 0; it < a.iters; ++it) {
-    int64_t b, l, m;
-    const bool valid = decode(it, b, l, m);
-    const RowCoef rc = row_coef(a, l, m);
-    const int64_t loff = ((b * a.nO + l) * a.nI + m) * (int64_t)nL;
-
-    // ---- right-hand side of the chunk ------------------------------------
-    double2 z[kCMax], ip[kCMax];
+    // ---- right-hand side, staged through LDS -------------------------------
 #pragma unroll
-    for (int j = 0; j < kCMax; ++j) {
-      const int x = x0 + j;
-      double2 d = make_double2(0, 0);
-      if (j < c && x < nL && valid) {
-        if (a.in) d = ld(reinterpret_cast<const TIN*>(a.in), loff + x);
-        if (a.PO) {
-          const int64_t pb = (b * 2) * (int64_t)a.nI * nL + m * (int64_t)nL + x;
-          d = cfma(a.alpha0[l], a.PO[pb], d);
-          d = cfma(a.alpha1[l], a.PO[pb + (int64_t)a.nI * nL], d);
+    for (int si = 0; si < SPW; ++si) {
+      uint32_t sb, sl, sm;
+      const bool sv = decode_line(a, g, t, LPB, it, wslot0 + si, sb, sl, sm);
+      const int64_t soff = ((int64_t)(sb * a.nO + sl) * a.nI + sm) * nL;
+      double2 al0 = make_double2(0, 0), al1 = al0, be0 = al0, be1 = al0;
+      if (a.PO) { al0 = a.alpha0[sl]; al1 = a.alpha1[sl]; }
+      if (a.PI) { be0 = a.beta0[sm]; be1 = a.beta1[sm]; }
+      const double2* po = a.PO ? a.PO + (int64_t)(sb * 2) * a.nI * nL + (int64_t)sm * nL : nullptr;
+      const double2* pi = a.PI ? a.PI + (int64_t)((sb * a.nO + sl) * 2) * nL : nullptr;
+      // one source at a time (each lane revisits only its own staging slots),
+      // so that at most kCMax loads are in flight per lane
+      if (a.in) {
+        double2 d[kCMax];
+#pragma unroll
+        for (int jj = 0; jj < kCMax; ++jj) {
+          const int r = jj * 64 + lane, x = wx0 + r;
+          d[jj] = (r < seg && x < nL && sv) ? to_d2(reinterpret_cast<const TIN*>(a.in)[soff + x])
+                                             : make_double2(0, 0);
         }
-        if (a.PI) {
-          const int64_t pb = ((b * a.nO + l) * 2) * (int64_t)nL + x;
-          d = cfma(a.beta0[m], a.PI[pb], d);
-          d = cfma(a.beta1[m], a.PI[pb + nL], d);
+#pragma unroll
+        for (int jj = 0; jj < kCMax; ++jj) {
+          const int r = jj * 64 + lane;
+          if (r < seg) S[stage_pos(si * seg + r)] = d[jj];
+        }
+      } else {
+#pragma unroll
+        for (int jj = 0; jj < kCMax; ++jj) {
+          const int r = jj * 64 + lane;
+          if (r < seg) S[stage_pos(si * seg + r)] = make_double2(0, 0);
         }
       }
-      z[j] = d;
-    }
-
-    // ---- 1. reciprocal pivots from the plan's factor table -----------------
-    const double2* pt = a.piv + (l * a.nI + m) * (int64_t)nL;
-    const double2 ip_in = (x0 > 0 && x0 - 1 < nL) ? pt[x0 - 1] : make_double2(0, 0);
+      if (po) {
 #pragma unroll
-    for (int j = 0; j < kCMax; ++j) {
-      const int x = x0 + j;
-      ip[j] = (j < c && x < nL) ? pt[x] : make_double2(1, 0);
+        for (int jj = 0; jj < kCMax; ++jj) {
+          const int r = jj * 64 + lane, x = wx0 + r;
+          if (r < seg && x < nL && sv) {
+            double2 d = S[stage_pos(si * seg + r)];
+            d = cfma(al0, po[x], d);
+            d = cfma(al1, po[(int64_t)a.nI * nL + x], d);
+            S[stage_pos(si * seg + r)] = d;
+          }
+        }
+      }
+      if (pi) {
+#pragma unroll
+        for (int jj = 0; jj < kCMax; ++jj) {
+          const int r = jj * 64 + lane, x = wx0 + r;
+          if (r < seg && x < nL && sv) {
+            double2 d = S[stage_pos(si * seg + r)];
+            d = cfma(be0, pi[x], d);
+            d = cfma(be1, pi[nL + x], d);
+            S[stage_pos(si * seg + r)] = d;
+          }
+        }
+      }
     }
 
-    // ---- 2. forward substitution: affine scan -----------------------------
+    uint32_t b, l, m;
+    const bool valid = decode_line(a, g, t, LPB, it, slot, b, l, m);
+    const RowCoef rc = row_coef(a, l, m);
+    double2 z[kCMax];
+#pragma unroll
+    for (int j = 0; j < kCMax; ++j) z[j] = j < c ? S[stage_pos(lane * c + j)] : make_double2(0, 0);
+
+    // ---- 1. forward substitution: affine scan -----------------------------
+    // Reciprocal pivots: the chunk's entering value from the plan's factor
+    // table, then the Thomas recurrence p_x = d_x - e^2 / p_{x-1}; they are
+    // parked in the lane's own staging slots (the right-hand side is in z).
     // z_x = f_x z_{x-1} + d_x with f_x = -e(x) / p_{x-1}.
+    const double2 ip_in = q > 0 ? a.piv[(int64_t)(l * a.nI + m) * P + q] : make_double2(0, 0);
     const double2 moff = make_double2(-rc.off.x, -rc.off.y);
     Aff A = aff_ident();
     {
-      double2 ipprev = ip_in;
+      double2 ipp = ip_in;
 #pragma unroll
       for (int j = 0; j < kCMax; ++j) {
         if (j < c) {
           const int x = x0 + j;
-          const double2 f = has_e(x, nL) ? cmul(moff, ipprev) : make_double2(0, 0);
+          const double2 f = has_e(x, nL) ? cmul(moff, ipp) : make_double2(0, 0);
           A.f = cmul(f, A.f);
           A.g = cfma(f, A.g, z[j]);
-          ipprev = ip[j];
+          double2 pv = diag_of(rc, x, nL);
+          if (has_e(x, nL)) pv = csub(pv, cmul(rc.off2, ipp));
+          ipp = x < nL ? crcp_fast(pv) : make_double2(1, 0);
+          S[stage_pos(lane * c + j)] = ipp;
         }
       }
     }
@@ -317,20 +379,21 @@ __global__ __launch_bounds__(NT) void lines_kernel(LineDev a) {
           const double2 f = has_e(x, nL) ? cmul(moff, ipprev) : make_double2(0, 0);
           zprev = cfma(f, zprev, z[j]);
           z[j] = zprev;
-          ipprev = ip[j];
+          ipprev = S[stage_pos(lane * c + j)];
         }
       }
     }
 
-    // ---- 3. back substitution: reversed affine scan -----------------------
+    // ---- 2. back substitution: reversed affine scan -----------------------
     // y_x = g_x y_{x+1} + h_x with g_x = -e(x+1)/p_x, h_x = z_x / p_x.
     Aff B = aff_ident();
 #pragma unroll
     for (int j = kCMax - 1; j >= 0; --j) {
       if (j < c) {
         const int x = x0 + j;
-        const double2 gx = has_e(x + 1, nL) ? cmul(moff, ip[j]) : make_double2(0, 0);
-        z[j] = cmul(z[j], ip[j]);  // h_x
+        const double2 ipj = S[stage_pos(lane * c + j)];
+        const double2 gx = has_e(x + 1, nL) ? cmul(moff, ipj) : make_double2(0, 0);
+        z[j] = cmul(z[j], ipj);  // h_x
         B.f = cmul(gx, B.f);
         B.g = cfma(gx, B.g, z[j]);
       }
@@ -342,7 +405,7 @@ __global__ __launch_bounds__(NT) void lines_kernel(LineDev a) {
       for (int j = kCMax - 1; j >= 0; --j) {
         if (j < c) {
           const int x = x0 + j;
-          const double2 gx = has_e(x + 1, nL) ? cmul(moff, ip[j]) : make_double2(0, 0);
+          const double2 gx = has_e(x + 1, nL) ? cmul(moff, S[stage_pos(lane * c + j)]) : make_double2(0, 0);
           ynext = cfma(gx, ynext, z[j]);
           z[j] = ynext;
         }
@@ -350,23 +413,32 @@ __global__ __launch_bounds__(NT) void lines_kernel(LineDev a) {
     }
 
     // ---- 4. epilogue -------------------------------------------------------
-    if (valid) {
-      if (a.out) {
-        TOUT* o = reinterpret_cast<TOUT*>(a.out);
+    if (a.out) {
 #pragma unroll
-        for (int j = 0; j < kCMax; ++j) {
-          const int x = x0 + j;
-          if (j < c && x < nL) o[loff + x] = from_d2<TOUT>(z[j]);
+      for (int j = 0; j < kCMax; ++j)
+        if (j < c) S[stage_pos(lane * c + j)] = z[j];
+      TOUT* o = reinterpret_cast<TOUT*>(a.out);
+#pragma unroll
+      for (int si = 0; si < SPW; ++si) {
+        uint32_t sb, sl, sm;
+        const bool sv = decode_line(a, g, t, LPB, it, wslot0 + si, sb, sl, sm);
+        const int64_t soff = ((int64_t)(sb * a.nO + sl) * a.nI + sm) * nL;
+#pragma unroll
+        for (int jj = 0; jj < kCMax; ++jj) {
+          const int r = jj * 64 + lane, x = wx0 + r;
+          if (r < seg && x < nL && sv) o[soff + x] = from_d2<TOUT>(S[stage_pos(si * seg + r)]);
         }
       }
-      if constexpr (RED) {
-        const int64_t wi = (a.red == 1) ? m : l;
+    }
+    if constexpr (RED) {
+      if (valid) {
+        const uint32_t wi = (a.red == 1) ? m : l;
         const double2 w0 = a.rho0[wi], w1 = a.rho1[wi];
 #pragma unroll
         for (int j = 0; j < kCMax; ++j) {
           if (j < c) {
-            accs[j * NT + tid] = cfma(w0, z[j], accs[j * NT + tid]);
-            accs[(c + j) * NT + tid] = cfma(w1, z[j], accs[(c + j) * NT + tid]);
+            acc0[j] = cfma(w0, z[j], acc0[j]);
+            acc1[j] = cfma(w1, z[j], acc1[j]);
           }
         }
       }
@@ -375,22 +447,32 @@ __global__ __launch_bounds__(NT) void lines_kernel(LineDev a) {
 
   // ---- cross-slot reduction (fixed slot order) and partial write -----------
   if constexpr (RED) {
-    __syncthreads();
-    double2* outp = a.part + (g * a.ntiles + t) * 2 * (int64_t)nL;
-    for (int e = tid; e < 2 * nL; e += NT) {
-      const int k = e >= nL, x = e - k * nL;
-      const int qq = x / c, j = x - qq * c;
-      double2 s = make_double2(0, 0);
-      for (int sl = 0; sl < LPB; ++sl) s = cadd(s, accs[(k * c + j) * NT + sl * P + qq]);
-      outp[e] = s;
+    double2* outp = a.part + ((int64_t)g * a.ntiles + t) * 2 * nL;
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      __syncthreads();
+#pragma unroll
+      for (int j = 0; j < kCMax; ++j)
+        if (j < c) S[stage_pos(lane * c + j)] = k ? acc1[j] : acc0[j];
+      __syncthreads();
+      for (int x = tid; x < nL; x += NT) {
+        const int qq = x / c, j = x - qq * c;
+        double2 s = make_double2(0, 0);
+        for (int sl = 0; sl < LPB; ++sl) {
+          const int owner = sl * P + qq;
+          s = cadd(s, stage[(owner >> 6) * AREA + stage_pos((owner & 63) * c + j)]);
+        }
+        outp[(int64_t)k * nL + x] = s;
+      }
     }
   }
 }
 
-// Factor table: for every line matrix (l, m) the reciprocal pivots 1/p_x of
-// its Thomas elimination.  Lane q composes the Moebius maps of its rows, a
-// scan over the lanes gives the pivot state entering each chunk, and the lane
-// re-runs its rows.  Runs once per plan; one block of P lanes per line.
+// Factor table: for every line matrix (l, m) and lane chunk q, the reciprocal
+// pivot 1/p_{qc-1} entering the chunk of the Thomas elimination.  Lane q
+// composes the Moebius maps of its rows and a scan over the lanes gives the
+// pivot state entering each chunk.  Runs once per plan; one block of P lanes
+// per line.  The solves regenerate the pivots inside each chunk from it.
 __global__ void factor_kernel(LineDev a, int P, double2* piv) {
   extern __shared__ double smem_d[];
   Mob* buf = reinterpret_cast<Mob*>(smem_d);
@@ -434,50 +516,44 @@ __global__ void factor_kernel(LineDev a, int P, double2* piv) {
     // state entering the chunk: E (1, 0)^T = (E.a, E.c), 1/p = E.c / E.a
     ip = cmul(E.c, crcp(E.a));
   }
-  for (int j = 0; j < a.c; ++j) {
-    const int x = x0 + j;
-    if (x >= a.nL) break;
-    double2 p = diag_of(rc, x, a.nL);
-    if (has_e(x, a.nL)) p = csub(p, cmul(rc.off2, ip));
-    ip = crcp(p);
-    piv[line * a.nL + x] = ip;
-  }
+  piv[line * P + q] = ip;
 }
 
-template <typename TIN, typename TOUT, int NT, int P>
-hipError_t launch_P(const LineDev& d, int64_t blocks, size_t, hipStream_t s) {
-  if (d.red) {
-    // 2 c NT complex accumulators (up to 128 KB at NT = 512: above the
-    // default dynamic LDS limit, so raise it for this kernel once).
-    const size_t lds = (size_t)2 * d.c * NT * sizeof(double2);
-    static bool attr = false;
-    if (!attr) {
-      const hipError_t e = hipFuncSetAttribute(
-          reinterpret_cast<const void*>(&lines_kernel<TIN, TOUT, NT, P, true>),
-          hipFuncAttributeMaxDynamicSharedMemorySize, 2 * kCMax * NT * (int)sizeof(double2));
-      if (e != hipSuccess) return e;
-      attr = true;
-    }
-    hipLaunchKernelGGL((lines_kernel<TIN, TOUT, NT, P, true>), dim3((unsigned)blocks), dim3(NT), lds, s, d);
-  } else {
-    hipLaunchKernelGGL((lines_kernel<TIN, TOUT, NT, P, false>), dim3((unsigned)blocks), dim3(NT), 0, s, d);
+template <typename TIN, typename TOUT, int NT, int P, bool RED>
+hipError_t launch_R(const LineDev& d, int64_t blocks, hipStream_t s) {
+  // staging areas: up to 72 KB at NT = 512, above the default dynamic LDS
+  // limit, so raise the limit for this kernel once
+  static bool attr = false;
+  if (!attr) {
+    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&lines_kernel<TIN, TOUT, NT, P, RED>),
+                                             hipFuncAttributeMaxDynamicSharedMemorySize,
+                                             (NT / 64) * 72 * kCMax * (int)sizeof(double2));
+    if (e != hipSuccess) return e;
+    attr = true;
   }
+  const size_t lds = (size_t)(NT / 64) * 72 * d.c * sizeof(double2);
+  hipLaunchKernelGGL((lines_kernel<TIN, TOUT, NT, P, RED>), dim3((unsigned)blocks), dim3(NT), lds, s, d);
   return hipGetLastError();
 }
 
+template <typename TIN, typename TOUT, int NT, int P>
+hipError_t launch_P(const LineDev& d, int64_t blocks, hipStream_t s) {
+  return d.red ? launch_R<TIN, TOUT, NT, P, true>(d, blocks, s) : launch_R<TIN, TOUT, NT, P, false>(d, blocks, s);
+}
+
 template <typename TIN, typename TOUT>
-hipError_t launch_typed(const LineDev& d, int P, int64_t blocks, size_t lds, hipStream_t s) {
+hipError_t launch_typed(const LineDev& d, int P, int64_t blocks, hipStream_t s) {
   switch (P) {
-    case 1: return launch_P<TIN, TOUT, 256, 1>(d, blocks, lds, s);
-    case 2: return launch_P<TIN, TOUT, 256, 2>(d, blocks, lds, s);
-    case 4: return launch_P<TIN, TOUT, 256, 4>(d, blocks, lds, s);
-    case 8: return launch_P<TIN, TOUT, 256, 8>(d, blocks, lds, s);
-    case 16: return launch_P<TIN, TOUT, 256, 16>(d, blocks, lds, s);
-    case 32: return launch_P<TIN, TOUT, 256, 32>(d, blocks, lds, s);
-    case 64: return launch_P<TIN, TOUT, 256, 64>(d, blocks, lds, s);
-    case 128: return launch_P<TIN, TOUT, 256, 128>(d, blocks, lds, s);
-    case 256: return launch_P<TIN, TOUT, 256, 256>(d, blocks, lds, s);
-    case 512: return launch_P<TIN, TOUT, 512, 512>(d, blocks, lds, s);
+    case 1: return launch_P<TIN, TOUT, 256, 1>(d, blocks, s);
+    case 2: return launch_P<TIN, TOUT, 256, 2>(d, blocks, s);
+    case 4: return launch_P<TIN, TOUT, 256, 4>(d, blocks, s);
+    case 8: return launch_P<TIN, TOUT, 256, 8>(d, blocks, s);
+    case 16: return launch_P<TIN, TOUT, 256, 16>(d, blocks, s);
+    case 32: return launch_P<TIN, TOUT, 256, 32>(d, blocks, s);
+    case 64: return launch_P<TIN, TOUT, 256, 64>(d, blocks, s);
+    case 128: return launch_P<TIN, TOUT, 256, 128>(d, blocks, s);
+    case 256: return launch_P<TIN, TOUT, 256, 256>(d, blocks, s);
+    case 512: return launch_P<TIN, TOUT, 512, 512>(d, blocks, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -526,6 +602,7 @@ hipError_t launch_line_factors(const LineArgs& a, double2* piv, hipStream_t s) {
 
 hipError_t launch_lines(LineArgs a, hipStream_t s) {
   if (a.nL < 3 || !a.piv) return hipErrorInvalidValue;
+  if ((int64_t)a.nb * a.nO * a.nI + a.tile >= 0x7fffffffLL) return hipErrorInvalidValue;
   int P, c, NT;
   lines_geometry(a.nL, &P, &c, &NT);
   if (P > 512) return hipErrorInvalidValue;
@@ -549,12 +626,11 @@ hipError_t launch_lines(LineArgs a, hipStream_t s) {
   d.iters = d.tile / LPB;
   if (blocks <= 0) return hipSuccess;
   if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
-  const size_t lds = (a.red && LPB > 1) ? (size_t)2 * a.nL * sizeof(double2) : 0;
   const bool in64 = a.in_kind == ST_C64, out64 = a.out_kind == ST_C64;
-  if (!in64 && !out64) return launch_typed<double2, double2>(d, P, blocks, lds, s);
-  if (in64 && out64) return launch_typed<float2, float2>(d, P, blocks, lds, s);
-  if (in64) return launch_typed<float2, double2>(d, P, blocks, lds, s);
-  return launch_typed<double2, float2>(d, P, blocks, lds, s);
+  if (!in64 && !out64) return launch_typed<double2, double2>(d, P, blocks, s);
+  if (in64 && out64) return launch_typed<float2, float2>(d, P, blocks, s);
+  if (in64) return launch_typed<float2, double2>(d, P, blocks, s);
+  return launch_typed<double2, float2>(d, P, blocks, s);
 }
 
 }  // namespace helm

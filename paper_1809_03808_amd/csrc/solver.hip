@@ -979,7 +979,9 @@ int helm_setup(int dim, const int64_t* grid, const double* h, double omega, uint
     const int nO = dim == 2 ? 1 : p->ax[0].n;
     const int nI = p->ax[dim - 2].n;
     const int fam = dim == 2 ? 2 : 4;
-    const size_t per = (size_t)nO * nI * p->nL;
+    int P, c, NT;
+    lines_geometry(p->nL, &P, &c, &NT);
+    const size_t per = (size_t)nO * nI * P;
     if (p->factors.ensure(per * fam * sizeof(double2)) != hipSuccess) return HELM_ENOMEM;
     for (int k = 0; k < fam; ++k) {
       LineArgs la;
