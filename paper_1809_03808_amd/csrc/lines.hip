@@ -239,28 +239,42 @@ __device__ inline int stage_pos(int e) { return e + (e >> 3); }
 // touch 64 cache lines per wave instruction.  Instead every wave loads the
 // rows of its lanes with consecutive lanes on consecutive rows (whole cache
 // lines per instruction), assembles the right-hand side there, and passes the
-// chunks through its own LDS area (64 c padded complex values); solutions to
-// be stored take the same route back.  The per-wave area is only touched by
-// its own wave, whose LDS accesses execute in program order, except in the
-// final cross-slot reduction, which is fenced by block barriers.
-template <typename TIN, typename TOUT, int NT, int P, bool RED>
+// chunks through its own LDS area (72 c complex values, padded); solutions to
+// be stored take the same route back.  Between the two, the area parks the
+// lane's reciprocal pivots and then its backward multipliers.  A wave's area
+// is only touched by that wave, whose LDS accesses execute in program order,
+// except in the final cross-slot reduction, which is fenced by block
+// barriers.
+//
+// C = 8: every line has exactly P * 8 rows (no padding rows).  Then the only
+// rows without a coupling to their predecessor / successor are x = 0 and
+// x = nL - 1, and neither needs a guard: the entering reciprocal pivot of lane
+// 0 is zero, which zeroes its first forward multiplier, and the last lane's
+// backward recurrence starts from y = 0, which annihilates its last backward
+// multiplier.  C = 0: chunk length a.c (<= kCMax) at run time, rows past the
+// end of the line are identity rows.
+template <typename T, int NT, int P, int C, bool RED>
 __global__ __launch_bounds__(NT) void lines_kernel(LineDev a) {
   constexpr int NW = NT / 64;
   constexpr int PW = P < 64 ? P : 64;     // lanes of one line inside a wave
   constexpr int SPW = 64 / PW;            // lines per wave
   constexpr int LPB = NT / P;             // lines per block
+  constexpr bool FIXED = C > 0;
   __shared__ Aff wbuf[NW + 1];
-  extern __shared__ double2 stage[];  // NW areas of AREA = 72 c padded values
+  extern __shared__ double2 stage[];      // NW areas of 72 c padded values
 
-  const int c = a.c, nL = a.nL;
+  const int c = FIXED ? C : a.c, nL = FIXED ? P * C : a.nL;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int slot = tid / P, q = tid - slot * P;
+  // a line spans whole waves when P >= 64: its index is then wave-uniform
+  const int slot = P >= 64 ? __builtin_amdgcn_readfirstlane(tid / P) : tid / P;
+  const int q = tid - slot * P;
   const int x0 = q * c;
   const int wslot0 = (wv * 64) / P;                   // first line slot of this wave
   const int wx0 = (P >= 64 ? (wv * 64) % P : 0) * c;  // first row this wave stages
   const int seg = PW * c;                             // rows of one line staged by this wave
-  const int AREA = 72 * c;
-  double2* S = stage + wv * AREA;
+  double2* S = stage + wv * (72 * c);
+  auto in_chunk = [&](int j) { return FIXED ? j < C : j < c; };
+  auto slot_of = [&](int j) { return stage_pos(lane * c + j); };
 
   const uint32_t blk = blockIdx.x;
   uint32_t g = 0, t = 0;
@@ -279,7 +293,7 @@ __global__ __launch_bounds__(NT) void lines_kernel(LineDev a) {
 
   for (int it = 0; it < a.iters; ++it) {
     // ---- right-hand side, staged through LDS -------------------------------
-#pragma unroll
+#pragma unroll 4
     for (int si = 0; si < SPW; ++si) {
       uint32_t sb, sl, sm;
       const bool sv = decode_line(a, g, t, LPB, it, wslot0 + si, sb, sl, sm);
@@ -296,7 +310,7 @@ __global__ __launch_bounds__(NT) void lines_kernel(LineDev a) {
 #pragma unroll
         for (int jj = 0; jj < kCMax; ++jj) {
           const int r = jj * 64 + lane, x = wx0 + r;
-          d[jj] = (r < seg && x < nL && sv) ? to_d2(reinterpret_cast<const TIN*>(a.in)[soff + x])
+          d[jj] = (r < seg && x < nL && sv) ? to_d2(reinterpret_cast<const T*>(a.in)[soff + x])
                                              : make_double2(0, 0);
         }
 #pragma unroll
@@ -340,60 +354,70 @@ __global__ __launch_bounds__(NT) void lines_kernel(LineDev a) {
     uint32_t b, l, m;
     const bool valid = decode_line(a, g, t, LPB, it, slot, b, l, m);
     const RowCoef rc = row_coef(a, l, m);
+    const double2 moff = make_double2(-rc.off.x, -rc.off.y);  // -e
     double2 z[kCMax];
 #pragma unroll
-    for (int j = 0; j < kCMax; ++j) z[j] = j < c ? S[stage_pos(lane * c + j)] : make_double2(0, 0);
+    for (int j = 0; j < kCMax; ++j) z[j] = in_chunk(j) ? S[slot_of(j)] : make_double2(0, 0);
 
-    // ---- 1. forward substitution: affine scan -----------------------------
+    // ---- 1. pivots and forward composition --------------------------------
     // Reciprocal pivots: the chunk's entering value from the plan's factor
-    // table, then the Thomas recurrence p_x = d_x - e^2 / p_{x-1}; they are
-    // parked in the lane's own staging slots (the right-hand side is in z).
-    // z_x = f_x z_{x-1} + d_x with f_x = -e(x) / p_{x-1}.
+    // table, then the Thomas recurrence p_x = d_x - e^2 / p_{x-1}.
+    // Forward substitution z_x = f_x z_{x-1} + d_x, f_x = -e / p_{x-1}: the
+    // lane composes its rows into one affine map.
     const double2 ip_in = q > 0 ? a.piv[(int64_t)(l * a.nI + m) * P + q] : make_double2(0, 0);
-    const double2 moff = make_double2(-rc.off.x, -rc.off.y);
     Aff A = aff_ident();
     {
       double2 ipp = ip_in;
 #pragma unroll
       for (int j = 0; j < kCMax; ++j) {
-        if (j < c) {
+        if (in_chunk(j)) {
           const int x = x0 + j;
-          const double2 f = has_e(x, nL) ? cmul(moff, ipp) : make_double2(0, 0);
+          double2 f = cmul(moff, ipp);
+          if (!FIXED && !has_e(x, nL)) f = make_double2(0, 0);
           A.f = cmul(f, A.f);
           A.g = cfma(f, A.g, z[j]);
-          double2 pv = diag_of(rc, x, nL);
-          if (has_e(x, nL)) pv = csub(pv, cmul(rc.off2, ipp));
-          ipp = x < nL ? crcp_fast(pv) : make_double2(1, 0);
-          S[stage_pos(lane * c + j)] = ipp;
+          double2 pv;
+          if (FIXED) {
+            pv = (j == 0 && q == 0) ? rc.dlo : ((j == C - 1 && q == P - 1) ? rc.dhi : rc.dint);
+            pv = csub(pv, cmul(rc.off2, ipp));  // ipp = 0 at x = 0
+            ipp = crcp_fast(pv);
+          } else {
+            pv = diag_of(rc, x, nL);
+            if (has_e(x, nL)) pv = csub(pv, cmul(rc.off2, ipp));
+            ipp = x < nL ? crcp_fast(pv) : make_double2(1, 0);
+          }
+          S[slot_of(j)] = ipp;
         }
       }
     }
     const Aff Ein = scan_fwd<P>(A, q, wbuf);
+
+    // ---- 2. forward values, scaled for the back substitution --------------
+    // h_x = z_x / p_x; the lane's slots now take the backward multipliers
+    // g_x = -e / p_x (zero where row x + 1 is past the end of the line).
     {
-      double2 zprev = Ein.g;
-      double2 ipprev = ip_in;
+      double2 zp = Ein.g;
+      double2 mp = cmul(moff, ip_in);
 #pragma unroll
       for (int j = 0; j < kCMax; ++j) {
-        if (j < c) {
+        if (in_chunk(j)) {
           const int x = x0 + j;
-          const double2 f = has_e(x, nL) ? cmul(moff, ipprev) : make_double2(0, 0);
-          zprev = cfma(f, zprev, z[j]);
-          z[j] = zprev;
-          ipprev = S[stage_pos(lane * c + j)];
+          const double2 f = (FIXED || has_e(x, nL)) ? mp : make_double2(0, 0);
+          zp = cfma(f, zp, z[j]);
+          const double2 ipj = S[slot_of(j)];
+          z[j] = cmul(zp, ipj);
+          mp = cmul(moff, ipj);
+          S[slot_of(j)] = (FIXED || has_e(x + 1, nL)) ? mp : make_double2(0, 0);
         }
       }
     }
 
-    // ---- 2. back substitution: reversed affine scan -----------------------
-    // y_x = g_x y_{x+1} + h_x with g_x = -e(x+1)/p_x, h_x = z_x / p_x.
+    // ---- 3. back substitution y_x = g_x y_{x+1} + h_x: composition, scan ---
     Aff B = aff_ident();
 #pragma unroll
     for (int j = kCMax - 1; j >= 0; --j) {
-      if (j < c) {
-        const int x = x0 + j;
-        const double2 ipj = S[stage_pos(lane * c + j)];
-        const double2 gx = has_e(x + 1, nL) ? cmul(moff, ipj) : make_double2(0, 0);
-        z[j] = cmul(z[j], ipj);  // h_x
+      if (in_chunk(j)) {
+        const double2 gx = S[slot_of(j)];
         B.f = cmul(gx, B.f);
         B.g = cfma(gx, B.g, z[j]);
       }
@@ -403,10 +427,8 @@ __global__ __launch_bounds__(NT) void lines_kernel(LineDev a) {
       double2 ynext = Bin.g;
 #pragma unroll
       for (int j = kCMax - 1; j >= 0; --j) {
-        if (j < c) {
-          const int x = x0 + j;
-          const double2 gx = has_e(x + 1, nL) ? cmul(moff, S[stage_pos(lane * c + j)]) : make_double2(0, 0);
-          ynext = cfma(gx, ynext, z[j]);
+        if (in_chunk(j)) {
+          ynext = cfma(S[slot_of(j)], ynext, z[j]);
           z[j] = ynext;
         }
       }
@@ -416,9 +438,9 @@ __global__ __launch_bounds__(NT) void lines_kernel(LineDev a) {
     if (a.out) {
 #pragma unroll
       for (int j = 0; j < kCMax; ++j)
-        if (j < c) S[stage_pos(lane * c + j)] = z[j];
-      TOUT* o = reinterpret_cast<TOUT*>(a.out);
-#pragma unroll
+        if (in_chunk(j)) S[slot_of(j)] = z[j];
+      T* o = reinterpret_cast<T*>(a.out);
+#pragma unroll 4
       for (int si = 0; si < SPW; ++si) {
         uint32_t sb, sl, sm;
         const bool sv = decode_line(a, g, t, LPB, it, wslot0 + si, sb, sl, sm);
@@ -426,7 +448,7 @@ __global__ __launch_bounds__(NT) void lines_kernel(LineDev a) {
 #pragma unroll
         for (int jj = 0; jj < kCMax; ++jj) {
           const int r = jj * 64 + lane, x = wx0 + r;
-          if (r < seg && x < nL && sv) o[soff + x] = from_d2<TOUT>(S[stage_pos(si * seg + r)]);
+          if (r < seg && x < nL && sv) o[soff + x] = from_d2<T>(S[stage_pos(si * seg + r)]);
         }
       }
     }
@@ -436,7 +458,7 @@ __global__ __launch_bounds__(NT) void lines_kernel(LineDev a) {
         const double2 w0 = a.rho0[wi], w1 = a.rho1[wi];
 #pragma unroll
         for (int j = 0; j < kCMax; ++j) {
-          if (j < c) {
+          if (in_chunk(j)) {
             acc0[j] = cfma(w0, z[j], acc0[j]);
             acc1[j] = cfma(w1, z[j], acc1[j]);
           }
@@ -453,14 +475,14 @@ __global__ __launch_bounds__(NT) void lines_kernel(LineDev a) {
       __syncthreads();
 #pragma unroll
       for (int j = 0; j < kCMax; ++j)
-        if (j < c) S[stage_pos(lane * c + j)] = k ? acc1[j] : acc0[j];
+        if (in_chunk(j)) S[slot_of(j)] = k ? acc1[j] : acc0[j];
       __syncthreads();
       for (int x = tid; x < nL; x += NT) {
         const int qq = x / c, j = x - qq * c;
         double2 s = make_double2(0, 0);
         for (int sl = 0; sl < LPB; ++sl) {
           const int owner = sl * P + qq;
-          s = cadd(s, stage[(owner >> 6) * AREA + stage_pos((owner & 63) * c + j)]);
+          s = cadd(s, stage[(owner >> 6) * (72 * c) + stage_pos((owner & 63) * c + j)]);
         }
         outp[(int64_t)k * nL + x] = s;
       }
@@ -519,41 +541,44 @@ __global__ void factor_kernel(LineDev a, int P, double2* piv) {
   piv[line * P + q] = ip;
 }
 
-template <typename TIN, typename TOUT, int NT, int P, bool RED>
+template <typename T, int NT, int P, int C, bool RED>
 hipError_t launch_R(const LineDev& d, int64_t blocks, hipStream_t s) {
   // staging areas: up to 72 KB at NT = 512, above the default dynamic LDS
   // limit, so raise the limit for this kernel once
   static bool attr = false;
   if (!attr) {
-    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&lines_kernel<TIN, TOUT, NT, P, RED>),
+    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&lines_kernel<T, NT, P, C, RED>),
                                              hipFuncAttributeMaxDynamicSharedMemorySize,
                                              (NT / 64) * 72 * kCMax * (int)sizeof(double2));
     if (e != hipSuccess) return e;
     attr = true;
   }
   const size_t lds = (size_t)(NT / 64) * 72 * d.c * sizeof(double2);
-  hipLaunchKernelGGL((lines_kernel<TIN, TOUT, NT, P, RED>), dim3((unsigned)blocks), dim3(NT), lds, s, d);
+  hipLaunchKernelGGL((lines_kernel<T, NT, P, C, RED>), dim3((unsigned)blocks), dim3(NT), lds, s, d);
   return hipGetLastError();
 }
 
-template <typename TIN, typename TOUT, int NT, int P>
+template <typename T, int NT, int P>
 hipError_t launch_P(const LineDev& d, int64_t blocks, hipStream_t s) {
-  return d.red ? launch_R<TIN, TOUT, NT, P, true>(d, blocks, s) : launch_R<TIN, TOUT, NT, P, false>(d, blocks, s);
+  const bool fixed = d.c == kCMax && d.nL == P * kCMax;
+  if (fixed)
+    return d.red ? launch_R<T, NT, P, kCMax, true>(d, blocks, s) : launch_R<T, NT, P, kCMax, false>(d, blocks, s);
+  return d.red ? launch_R<T, NT, P, 0, true>(d, blocks, s) : launch_R<T, NT, P, 0, false>(d, blocks, s);
 }
 
-template <typename TIN, typename TOUT>
+template <typename T>
 hipError_t launch_typed(const LineDev& d, int P, int64_t blocks, hipStream_t s) {
   switch (P) {
-    case 1: return launch_P<TIN, TOUT, 256, 1>(d, blocks, s);
-    case 2: return launch_P<TIN, TOUT, 256, 2>(d, blocks, s);
-    case 4: return launch_P<TIN, TOUT, 256, 4>(d, blocks, s);
-    case 8: return launch_P<TIN, TOUT, 256, 8>(d, blocks, s);
-    case 16: return launch_P<TIN, TOUT, 256, 16>(d, blocks, s);
-    case 32: return launch_P<TIN, TOUT, 256, 32>(d, blocks, s);
-    case 64: return launch_P<TIN, TOUT, 256, 64>(d, blocks, s);
-    case 128: return launch_P<TIN, TOUT, 256, 128>(d, blocks, s);
-    case 256: return launch_P<TIN, TOUT, 256, 256>(d, blocks, s);
-    case 512: return launch_P<TIN, TOUT, 512, 512>(d, blocks, s);
+    case 1: return launch_P<T, 256, 1>(d, blocks, s);
+    case 2: return launch_P<T, 256, 2>(d, blocks, s);
+    case 4: return launch_P<T, 256, 4>(d, blocks, s);
+    case 8: return launch_P<T, 256, 8>(d, blocks, s);
+    case 16: return launch_P<T, 256, 16>(d, blocks, s);
+    case 32: return launch_P<T, 256, 32>(d, blocks, s);
+    case 64: return launch_P<T, 256, 64>(d, blocks, s);
+    case 128: return launch_P<T, 256, 128>(d, blocks, s);
+    case 256: return launch_P<T, 256, 256>(d, blocks, s);
+    case 512: return launch_P<T, 512, 512>(d, blocks, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -626,11 +651,10 @@ hipError_t launch_lines(LineArgs a, hipStream_t s) {
   d.iters = d.tile / LPB;
   if (blocks <= 0) return hipSuccess;
   if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
-  const bool in64 = a.in_kind == ST_C64, out64 = a.out_kind == ST_C64;
-  if (!in64 && !out64) return launch_typed<double2, double2>(d, P, blocks, s);
-  if (in64 && out64) return launch_typed<float2, float2>(d, P, blocks, s);
-  if (in64) return launch_typed<float2, double2>(d, P, blocks, s);
-  return launch_typed<double2, float2>(d, P, blocks, s);
+  // one storage kind for the input and output lines
+  if ((a.in && a.out && a.in_kind != a.out_kind)) return hipErrorInvalidValue;
+  const int kind = a.in ? a.in_kind : a.out_kind;
+  return kind == ST_C64 ? launch_typed<float2>(d, P, blocks, s) : launch_typed<double2>(d, P, blocks, s);
 }
 
 }  // namespace helm
