@@ -152,6 +152,44 @@ const char* helm_kernel_name(int k);
 /* Release the plan and its device memory (synchronises the device first). */
 void helm_destroy(helm_plan* p);
 
+/*
+ * Batches: many independent problems (uneven grids, omega, precision) solved
+ * by one graph launch.  The method is applied to every problem unchanged
+ * (Sections 4.2, 5.2); batching is a scheduling layer above it.
+ *
+ * helm_batch_create -- group `count` distinct plans (same device; a plan may
+ *   belong to one batch at a time and must not be solved on its own while the
+ *   batch runs).  Each plan's workspace is sized for max_nrhs right-hand
+ *   sides now.  The batch owns side streams but not the plans.
+ *   Errors: HELM_EINVAL, HELM_ENOMEM, HELM_EDEVICE.
+ *
+ * helm_batch_solve -- u[i] = A_i^{-1} f[i] for every plan i, nrhs[i] <= max_nrhs
+ *   right-hand sides each, same layout and ownership as helm_solve.  On the
+ *   first call, or when any pointer, count or the stream differs from the
+ *   previous call, it solves each problem once eagerly on `stream` (this also
+ *   sets the refinement depth: one step more than those inputs needed, at
+ *   least 2, at most the plan's max_iter), then captures every problem's
+ *   complete solve into one graph, the problems on parallel branches, and
+ *   instantiates it.  Every call then launches that graph on `stream` and
+ *   returns without synchronising.  Checked plans (mixed precision, or
+ *   opt.check) refine under device control: a residual check kernel stops
+ *   the refinement of a problem by raising a flag that makes its remaining
+ *   launches return at once.
+ *   Errors: HELM_EINVAL, HELM_ENOMEM, HELM_EDEVICE, or the status of a
+ *   failing eager solve.
+ *
+ * helm_batch_report_get -- report of problem i from the last batch solve
+ *   (synchronises the stream of that solve).  status HELM_ENOCONV if the
+ *   captured refinement depth did not reach tol, HELM_ENONFINITE for NaN/Inf.
+ */
+typedef struct helm_batch helm_batch;
+int helm_batch_create(helm_plan* const* plans, int count, int max_nrhs, helm_batch** out);
+int helm_batch_solve(helm_batch* b, const void* const* f, void* const* u, const int* nrhs,
+                     void* stream);
+int helm_batch_report_get(helm_batch* b, int i, helm_report* out);
+/* Release the batch (synchronises the device first); the plans stay valid. */
+void helm_batch_destroy(helm_batch* b);
+
 /* Static description of a status code. */
 const char* helm_strerror(int code);
 

@@ -21,7 +21,8 @@ constexpr int kMidThreads = 256;
 
 __global__ __launch_bounds__(kMidThreads) void sum_partials_kernel(const double2* __restrict__ part,
                                                                    int64_t ngroups, int ntiles, int nL,
-                                                                   double2* __restrict__ out) {
+                                                                   double2* __restrict__ out, const int* skip) {
+  if (skip && *skip) return;
   const int64_t i = (int64_t)blockIdx.x * kMidThreads + threadIdx.x;
   const int64_t per = 2 * (int64_t)nL;
   if (i >= ngroups * per) return;
@@ -43,6 +44,7 @@ constexpr int kMidOut = kMidCols - 2;
 __global__ __launch_bounds__(kMidThreads) void inner_mid_kernel(InnerMidArgs a) {
   __shared__ double2 sl[kMidSlices][2][kMidCols];
   __shared__ double2 v[2][kMidCols];
+  if (a.skip && *a.skip) return;
   const int nL = a.nL;
   const int ntx = (nL + kMidOut - 1) / kMidOut;
   const int64_t g = blockIdx.x / ntx;
@@ -110,6 +112,7 @@ __global__ __launch_bounds__(kMidThreads) void inner_mid_kernel(InnerMidArgs a) 
 
 // Outer operator on physical planes [nb][2][n2][n3]; one thread per (b, i2, i3).
 __global__ __launch_bounds__(kMidThreads) void outer_mid_kernel(OuterMidArgs a) {
+  if (a.skip && *a.skip) return;
   const int64_t plane = (int64_t)a.n2 * a.n3;
   const int64_t idx = (int64_t)blockIdx.x * kMidThreads + threadIdx.x;
   if (idx >= (int64_t)a.nb * plane) return;
@@ -153,12 +156,12 @@ __global__ __launch_bounds__(kMidThreads) void outer_mid_kernel(OuterMidArgs a) 
 }  // namespace
 
 hipError_t launch_sum_partials(const double2* part, int ngroups, int ntiles, int nL, double2* out,
-                               hipStream_t s) {
+                               const int* skip, hipStream_t s) {
   const int64_t n = (int64_t)ngroups * 2 * nL;
   if (n <= 0) return hipSuccess;
   const int64_t blocks = (n + kMidThreads - 1) / kMidThreads;
   hipLaunchKernelGGL(sum_partials_kernel, dim3((unsigned)blocks), dim3(kMidThreads), 0, s, part,
-                     (int64_t)ngroups, ntiles, nL, out);
+                     (int64_t)ngroups, ntiles, nL, out, skip);
   return hipGetLastError();
 }
 

@@ -155,6 +155,7 @@ struct LineArgs {
   const double2* piv = nullptr;  // [nO*nI][P] reciprocal pivot entering each lane chunk
   int tile = 0;    // lines per workgroup tile
   int ntiles = 0;  // tiles along the reduced (or flattened) index
+  const int* skip = nullptr;     // device flag: the launch does nothing while *skip != 0
 };
 
 hipError_t launch_lines(LineArgs a, hipStream_t s);
@@ -193,12 +194,13 @@ struct InnerMidArgs {
   BDiff d;
   double hL;
   double2 kLo, kHi;
+  const int* skip = nullptr;
 };
 hipError_t launch_inner_mid(const InnerMidArgs& a, hipStream_t s);
 
 // Sum partial planes: out[g][k][:] = sum_t part[g ntiles + t][k][:], g < ngroups.
 hipError_t launch_sum_partials(const double2* part, int ngroups, int ntiles, int nL,
-                               double2* out, hipStream_t s);
+                               double2* out, const int* skip, hipStream_t s);
 
 // Outer boundary operator on physical (x2, x3) planes (3D):
 //   r[b][k] = sum_k' (dK1 - w^2 dM1)[k][k'] (M2 (x) M3) v_k' + dM1[k][k'] (K2 (x) M3 + M2 (x) K3) v_k'
@@ -212,6 +214,7 @@ struct OuterMidArgs {
   double w2;
   double h2, h3;
   double2 k2Lo, k2Hi, k3Lo, k3Hi;
+  const int* skip = nullptr;
 };
 hipError_t launch_outer_mid(const OuterMidArgs& a, hipStream_t s);
 
@@ -234,6 +237,7 @@ struct ResidArgs {
   double* norms;  // device [nb][2]: sum |r|^2, sum |f|^2 (accumulated by the finishing kernel)
   double* scratch;
   int64_t scratch_len;
+  const int* skip = nullptr;  // device flag: nothing is computed while *skip != 0
 };
 hipError_t launch_residual(const ResidArgs& a, hipStream_t s);
 int64_t residual_scratch_len(int dim, const int64_t* grid, int nb);

@@ -173,6 +173,7 @@ struct LineDev {
   const double2* piv;   // [nO*nI][P]: reciprocal pivot entering the chunk of each lane
   void* out;
   double2* part;
+  const int* skip;
 };
 
 struct RowCoef {
@@ -262,6 +263,7 @@ __global__ __launch_bounds__(NT) void lines_kernel(LineDev a) {
   constexpr bool FIXED = C > 0;
   __shared__ Aff wbuf[NW + 1];
   extern __shared__ double2 stage[];      // NW areas of 72 c padded values
+  if (a.skip && *a.skip) return;
 
   const int c = FIXED ? C : a.c, nL = FIXED ? P * C : a.nL;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -599,6 +601,7 @@ LineDev make_dev(const LineArgs& a, int P, int c) {
   d.rho0 = a.rho0; d.rho1 = a.rho1;
   d.piv = a.piv;
   d.out = a.out; d.part = a.part;
+  d.skip = a.skip;
   d.tile = d.ntiles = d.iters = 0;
   (void)P;
   return d;

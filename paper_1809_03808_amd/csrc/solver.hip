@@ -108,6 +108,8 @@ struct helm_plan {
   // [3] = (A, A); 2D uses [0], [1].
   helm::DevMem factors;
   const double2* seed[4] = {nullptr, nullptr, nullptr, nullptr};
+  // device-side refinement control (IrCtl) for captured solves
+  helm::DevMem ctl;
   std::vector<double> h_norms;
   helm_report rep{};
   // per-kernel event timing
@@ -117,6 +119,8 @@ struct helm_plan {
     double bytes;
   };
   bool prof = false;
+  // device flag read by every launch while set (captured refinement steps)
+  const int* skip_cur = nullptr;
   std::vector<Ev> evs;
   size_t nev = 0;
   helm_kernel_stats kst{};
@@ -328,7 +332,7 @@ int run_pow2(helm_plan* p, int L, int na, int nb, int sign, bool fp32, const voi
     f.scale = scale;
     f.scale_c = scale_c;
     f.cmode = cmode;
-    f.skip = skip;
+    f.skip = skip ? skip : p->skip_cur;
     f.tw = fp32 ? r->f.p : r->d.p;
     const double by = (double)O * L * S * (esz_of(in_kind) + esz_of(out_kind));
     HCHK(timed(p, fp32 ? K_FFT32 : K_FFT64, by, st, [&] { return launch_fft_pass(f, fp32, in, out, st); }));
@@ -355,7 +359,7 @@ int run_pow2(helm_plan* p, int L, int na, int nb, int sign, bool fp32, const voi
   f1.in_kind = in_kind;
   f1.out_kind = tmp_kind;
   f1.sign = sign;
-  f1.skip = skip;
+  f1.skip = skip ? skip : p->skip_cur;
   f1.tw = fp32 ? r1->f.p : r1->d.p;
   f1.tw4 = fp32 ? rn->f.p : rn->d.p;
   const double by1 = (double)O * L * S * (esz_of(in_kind) + esz_of(tmp_kind));
@@ -379,7 +383,7 @@ int run_pow2(helm_plan* p, int L, int na, int nb, int sign, bool fp32, const voi
   f2.scale = scale;
   f2.scale_c = scale_c;
   f2.cmode = cmode;
-  f2.skip = skip;
+  f2.skip = skip ? skip : p->skip_cur;
   f2.tw = fp32 ? r2->f.p : r2->d.p;
   const double by2 = (double)O * L * S * (esz_of(tmp_kind) + esz_of(out_kind));
   HCHK(timed(p, fp32 ? K_FFT32 : K_FFT64, by2, st, [&] { return launch_fft_pass(f2, fp32, tmp, out, st); }));
@@ -407,7 +411,7 @@ int run_fft(helm_plan* p, const PAxis& a, int sign, bool fp32, const void* in, i
   c.M = a.M;
   c.S = S;
   c.w = fp32 ? a.chirp_f[si] : a.chirp_d[si];
-  c.skip = skip;
+  c.skip = skip ? skip : p->skip_cur;
   c.post = 0;
   c.in_kind = in_kind;
   c.out_kind = T;
@@ -484,6 +488,7 @@ int inner_solve(helm_plan* p, const Level& lv, const InnerIO& io, hipStream_t st
   const PAxis& I = *lv.inner;
   const double2 sC = make_double2(-lv.w2, 0.0);
   LineArgs base;
+  base.skip = p->skip_cur;
   base.nb = lv.nb;
   base.nO = lv.nO;
   base.nI = lv.nI;
@@ -516,6 +521,7 @@ int inner_solve(helm_plan* p, const Level& lv, const InnerIO& io, hipStream_t st
   HCHK(timed(p, K_LINES, io.in ? elems * esz_of(io.in_kind) : 0.0, st, [&] { return launch_lines(s1, st); }));
 
   InnerMidArgs m;
+  m.skip = p->skip_cur;
   m.nb = lv.nb;
   m.nO = lv.nO;
   m.nL = lv.nL;
@@ -588,7 +594,8 @@ int inner_solve(helm_plan* p, const Level& lv, const InnerIO& io, hipStream_t st
 
 // Sum reduce-over-l partials [b][m][t][k][x] into planes [b][k][m][x].
 __global__ void sum_to_planes_kernel(const double2* __restrict__ part, int nb, int nI, int nL, int ntiles,
-                                     double2* __restrict__ out) {
+                                     double2* __restrict__ out, const int* skip) {
+  if (skip && *skip) return;
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const int64_t total = (int64_t)nb * 2 * nI * nL;
   if (i >= total) return;
@@ -608,7 +615,7 @@ int sum_to_planes(helm_plan* p, const Level& lv, double2* out, hipStream_t st) {
   const int64_t total = (int64_t)lv.nb * 2 * lv.nI * lv.nL;
   HCHK(timed(p, K_SUM, (double)total * sizeof(double2) * (ntl + 1), st, [&] {
     hipLaunchKernelGGL(sum_to_planes_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st,
-                       p->part.as<double2>(), lv.nb, lv.nI, lv.nL, ntl, out);
+                       p->part.as<double2>(), lv.nb, lv.nI, lv.nL, ntl, out, p->skip_cur);
     return hipGetLastError();
   }));
   return HELM_OK;
@@ -676,6 +683,7 @@ int solve_once(helm_plan* p, const void* x, int x_kind, double2* u, int accumula
   // Outer step 2: r = C_1 v_b, w_b.
   {
     OuterMidArgs om;
+    om.skip = p->skip_cur;
     om.nb = nb;
     om.n2 = n2;
     om.n3 = n3;
@@ -793,12 +801,14 @@ int ensure_workspace(helm_plan* p, int nb, bool fp32, bool need_r) {
   }
   HCHK(p->scratch.ensure((size_t)residual_scratch_len(p->dim, p->grid, nb) * sizeof(double)));
   HCHK(p->norms.ensure((size_t)nb * 2 * sizeof(double)));
+  HCHK(p->ctl.ensure(64));
   p->h_norms.resize(2 * nb);
   return HELM_OK;
 }
 
 ResidArgs resid_args(helm_plan* p, int nb) {
   ResidArgs a;
+  a.skip = p->skip_cur;
   a.dim = p->dim;
   a.nb = nb;
   for (int j = 0; j < p->dim; ++j) {
@@ -877,11 +887,145 @@ void fill_axis_tables_host(PAxis& a, double omega, std::vector<double2>& buf, st
   (void)omega;
 }
 
+
+// ---------------------------------------------------------------------------
+// Refinement controlled on the device, for solves captured in a graph: the
+// host cannot inspect residual norms between the steps, so a one-thread
+// kernel evaluates them and raises a flag that turns every later launch of
+// the same problem into an immediate return.
+// ---------------------------------------------------------------------------
+struct IrCtl {
+  int done;        // nonzero: converged or failed, later launches return at once
+  int iters;       // refinement steps taken after the first solve
+  int status;      // HELM_* of the solve
+  int pad;
+  double rel_first;
+  double rel_last;
+};
+
+__global__ void ir_reset_kernel(IrCtl* c, int done) {
+  c->done = done;
+  c->iters = 0;
+  c->status = HELM_OK;
+  c->pad = 0;
+  c->rel_first = -1.0;
+  c->rel_last = -1.0;
+}
+
+// After the residual of stage k (k = 0: first solve): converged, failed or
+// one more refinement step.  Same rule as the host loop of helm_solve: stop
+// at tol, at max_iter steps, or when a step fails to halve the residual.
+__global__ void ir_check_kernel(const double* norms, int nb, double tol, int max_steps, int stage, IrCtl* c) {
+  if (c->done) return;
+  double mx = 0.0;
+  bool bad = false;
+  for (int b = 0; b < nb; ++b) {
+    const double rr = norms[2 * b], ff = norms[2 * b + 1];
+    if (!isfinite(rr) || !isfinite(ff)) bad = true;
+    const double v = ff > 0.0 ? sqrt(rr / ff) : 0.0;
+    mx = fmax(mx, v);
+  }
+  if (bad) {
+    c->status = HELM_ENONFINITE;
+    c->rel_last = NAN;
+    c->done = 1;
+    return;
+  }
+  const double prev = c->rel_last;
+  if (stage == 0) c->rel_first = mx;
+  c->rel_last = mx;
+  if (mx <= tol) {
+    c->status = HELM_OK;
+    c->done = 1;
+  } else if (stage >= max_steps || (stage > 0 && !(mx < 0.5 * prev))) {
+    c->status = HELM_ENOCONV;
+    c->done = 1;
+  } else {
+    c->iters = stage + 1;
+  }
+}
+
+// Enqueue one problem's complete solve with `steps` refinement steps whose
+// launches are skipped on the device once the residual criterion is met.
+// Nothing here allocates or synchronises (the workspace must be in place).
+int enqueue_device_ir(helm_plan* p, const double2* F, double2* U, int nb, int steps, hipStream_t st) {
+  const bool mixed = p->opt.precision == HELM_PREC_MIXED;
+  const bool check = mixed || p->opt.check;
+  IrCtl* c = p->ctl.as<IrCtl>();
+  const bool prof = p->prof;
+  p->prof = false;
+  p->skip_cur = nullptr;
+  int rc = HELM_OK;
+  do {
+    hipLaunchKernelGGL(ir_reset_kernel, dim3(1), dim3(1), 0, st, c, check ? 0 : 1);
+    if (hipGetLastError() != hipSuccess) { rc = HELM_EDEVICE; break; }
+    rc = solve_once(p, F, ST_C128, U, 0, nb, mixed, st);
+    if (rc || !check) break;
+    const int rk = mixed ? ST_C64 : ST_C128;
+    for (int k = 0; k <= steps && !rc; ++k) {
+      if (k > 0) {
+        p->skip_cur = &c->done;
+        rc = solve_once(p, p->R.p, rk, U, 1, nb, mixed, st);
+        if (rc) break;
+      }
+      ResidArgs a = resid_args(p, nb);
+      a.u = U;
+      a.f = F;
+      a.r = p->R.p;
+      a.r_kind = rk;
+      if (launch_residual(a, st) != hipSuccess) { rc = HELM_EDEVICE; break; }
+      hipLaunchKernelGGL(ir_check_kernel, dim3(1), dim3(1), 0, st, (const double*)a.norms, nb, p->opt.tol,
+                         steps, k, c);
+      if (hipGetLastError() != hipSuccess) rc = HELM_EDEVICE;
+    }
+  } while (false);
+  p->skip_cur = nullptr;
+  p->prof = prof;
+  return rc;
+}
+
 }  // namespace
 
 }  // namespace helm
 
 using namespace helm;
+
+// A batch of independent plans solved by one graph launch.  Each plan keeps
+// its own workspace; the plans' pipelines are spread over side streams
+// inside one stream capture (longest first onto the least loaded stream), so
+// the graph has one independent branch per stream.
+struct helm_batch {
+  std::vector<helm_plan*> plans;
+  int max_nrhs = 1;
+  int device = 0;
+  hipStream_t cap = nullptr;  // capture origin (the legacy default stream cannot be captured)
+  std::vector<hipStream_t> side;
+  std::vector<hipEvent_t> join;
+  hipEvent_t fork = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  // inputs the current graph was captured for
+  std::vector<const void*> kf;
+  std::vector<void*> ku;
+  std::vector<int> kn;
+  hipStream_t kst = nullptr;
+  std::vector<int> steps;  // refinement steps captured per plan
+  hipStream_t last = nullptr;
+  void drop_graph() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    exec = nullptr;
+    graph = nullptr;
+  }
+  ~helm_batch() {
+    (void)hipDeviceSynchronize();
+    drop_graph();
+    for (auto s : side) (void)hipStreamDestroy(s);
+    if (cap) (void)hipStreamDestroy(cap);
+    for (auto e : join) (void)hipEventDestroy(e);
+    if (fork) (void)hipEventDestroy(fork);
+  }
+};
 
 extern "C" {
 
@@ -1105,5 +1249,135 @@ void helm_destroy(helm_plan* p) {
   (void)hipDeviceSynchronize();
   delete p;
 }
+
+int helm_batch_create(helm_plan* const* plans, int count, int max_nrhs, helm_batch** out) {
+  if (!out) return HELM_EINVAL;
+  *out = nullptr;
+  if (!plans || count < 1 || max_nrhs < 1) return HELM_EINVAL;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return HELM_EDEVICE;
+  std::vector<helm_plan*> v(plans, plans + count);
+  for (int i = 0; i < count; ++i) {
+    if (!v[i] || v[i]->device != dev) return HELM_EINVAL;
+    for (int j = 0; j < i; ++j)
+      if (v[j] == v[i]) return HELM_EINVAL;  // a plan's workspace serves one problem
+  }
+  std::unique_ptr<helm_batch> b(new (std::nothrow) helm_batch());
+  if (!b) return HELM_ENOMEM;
+  b->plans = v;
+  b->max_nrhs = max_nrhs;
+  b->device = dev;
+  for (helm_plan* p : v) {
+    const bool mixed = p->opt.precision == HELM_PREC_MIXED;
+    const int rc = ensure_workspace(p, max_nrhs, mixed, mixed || p->opt.check);
+    if (rc) return rc;
+  }
+  const int ns = std::min(count, 8);
+  for (int k = 0; k < ns; ++k) {
+    hipStream_t s;
+    hipEvent_t e;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return HELM_EDEVICE;
+    b->side.push_back(s);
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return HELM_EDEVICE;
+    b->join.push_back(e);
+  }
+  if (hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess) return HELM_EDEVICE;
+  if (hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess) return HELM_EDEVICE;
+  *out = b.release();
+  return HELM_OK;
+}
+
+int helm_batch_solve(helm_batch* b, const void* const* f, void* const* u, const int* nrhs, void* stream) {
+  if (!b || !f || !u || !nrhs) return HELM_EINVAL;
+  const int n = (int)b->plans.size();
+  for (int i = 0; i < n; ++i) {
+    if (!f[i] || !u[i] || f[i] == u[i] || nrhs[i] < 1 || nrhs[i] > b->max_nrhs) return HELM_EINVAL;
+  }
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  bool same = b->exec && b->kst == st;
+  for (int i = 0; same && i < n; ++i) same = b->kf[i] == f[i] && b->ku[i] == u[i] && b->kn[i] == nrhs[i];
+  if (!same) {
+    b->drop_graph();
+    // Eager solves first: they create every lazily built table (twiddles,
+    // chirps) outside the capture and give the refinement depth to capture:
+    // one step more than these inputs needed, at least 2, at most max_iter.
+    b->steps.assign(n, 0);
+    for (int i = 0; i < n; ++i) {
+      helm_plan* p = b->plans[i];
+      const int rc = helm_solve(p, f[i], u[i], nrhs[i], stream);
+      if (rc != HELM_OK && rc != HELM_ENOCONV) return rc;
+      b->steps[i] = std::min(p->opt.max_iter, std::max(2, p->rep.iterations + 1));
+    }
+    if (hipStreamSynchronize(st) != hipSuccess) return HELM_EDEVICE;
+    // longest problems first, each onto the stream with the least work
+    std::vector<int> order(n);
+    for (int i = 0; i < n; ++i) order[i] = i;
+    auto work = [&](int i) { return (double)npoints(b->plans[i]) * nrhs[i] * (1 + b->steps[i]); };
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return work(x) > work(y); });
+    const int ns = (int)b->side.size();
+    std::vector<double> load(ns, 0.0);
+    int rc = HELM_OK;
+    hipStream_t cs = b->cap;
+    if (hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed) != hipSuccess) return HELM_EDEVICE;
+    do {
+      if (hipEventRecord(b->fork, cs) != hipSuccess) { rc = HELM_EDEVICE; break; }
+      for (int k = 0; k < ns; ++k)
+        if (hipStreamWaitEvent(b->side[k], b->fork, 0) != hipSuccess) rc = HELM_EDEVICE;
+      if (rc) break;
+      for (int i : order) {
+        const int k = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        load[k] += work(i);
+        rc = enqueue_device_ir(b->plans[i], reinterpret_cast<const double2*>(f[i]),
+                               reinterpret_cast<double2*>(u[i]), nrhs[i], b->steps[i], b->side[k]);
+        if (rc) break;
+      }
+      // join every side stream back (also after an error, so that the
+      // capture can end)
+      for (int k = 0; k < ns; ++k) {
+        if (hipEventRecord(b->join[k], b->side[k]) != hipSuccess) rc = HELM_EDEVICE;
+        if (hipStreamWaitEvent(cs, b->join[k], 0) != hipSuccess) rc = HELM_EDEVICE;
+      }
+    } while (false);
+    hipGraph_t g = nullptr;
+    const hipError_t ce = hipStreamEndCapture(cs, &g);
+    if (rc || ce != hipSuccess || !g) {
+      if (g) (void)hipGraphDestroy(g);
+      (void)hipGetLastError();
+      return rc ? rc : HELM_EDEVICE;
+    }
+    b->graph = g;
+    if (hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0) != hipSuccess) {
+      b->drop_graph();
+      return HELM_EDEVICE;
+    }
+    b->kf.assign(f, f + n);
+    b->ku.assign(u, u + n);
+    b->kn.assign(nrhs, nrhs + n);
+    b->kst = st;
+  }
+  if (hipGraphLaunch(b->exec, st) != hipSuccess) return HELM_EDEVICE;
+  b->last = st;
+  return HELM_OK;
+}
+
+int helm_batch_report_get(helm_batch* b, int i, helm_report* out) {
+  if (!b || !out || i < 0 || i >= (int)b->plans.size()) return HELM_EINVAL;
+  if (!b->exec) return HELM_EINVAL;
+  if (hipStreamSynchronize(b->last) != hipSuccess) return HELM_EDEVICE;
+  helm_plan* p = b->plans[i];
+  IrCtl c;
+  if (hipMemcpy(&c, p->ctl.p, sizeof(IrCtl), hipMemcpyDeviceToHost) != hipSuccess) return HELM_EDEVICE;
+  helm_report r{};
+  r.status = c.status;
+  r.iterations = c.iters;
+  r.precision = p->opt.precision;
+  r.nrhs = b->kn[i];
+  r.rel_residual_max = c.rel_last;
+  r.rel_residual_first = c.rel_first;
+  *out = r;
+  return HELM_OK;
+}
+
+void helm_batch_destroy(helm_batch* b) { delete b; }
 
 }  // extern "C"

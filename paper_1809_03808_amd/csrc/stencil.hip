@@ -46,6 +46,7 @@ template <typename TR>
 __global__ __launch_bounds__(kResThreads) void residual_kernel(ResidArgs a, int64_t per_rhs,
                                                                int64_t quads_per_rhs, int64_t blocks_per_rhs) {
   __shared__ double red[2][kResThreads];
+  if (a.skip && *a.skip) return;
   const int64_t b = blockIdx.x / blocks_per_rhs;
   const int64_t qi = (blockIdx.x % blocks_per_rhs) * kResThreads + threadIdx.x;
   double sr = 0.0, sf = 0.0;
@@ -139,8 +140,9 @@ __global__ __launch_bounds__(kResThreads) void residual_kernel(ResidArgs a, int6
 }
 
 __global__ __launch_bounds__(kFinThreads) void norm_finish_kernel(const double* scratch, int64_t blocks_per_rhs,
-                                                                  double* norms) {
+                                                                  double* norms, const int* skip) {
   __shared__ double red[2][kFinThreads];
+  if (skip && *skip) return;
   const int64_t b = blockIdx.x;
   double sr = 0.0, sf = 0.0;
   for (int64_t i = threadIdx.x; i < blocks_per_rhs; i += kFinThreads) {
@@ -194,7 +196,7 @@ hipError_t launch_residual(const ResidArgs& a, hipStream_t s) {
     hipLaunchKernelGGL(residual_kernel<double2>, dim3((unsigned)blocks), dim3(kResThreads), 0, s, a, per, quads, bpr);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(norm_finish_kernel, dim3((unsigned)a.nb), dim3(kFinThreads), 0, s, a.scratch, bpr, a.norms);
+  hipLaunchKernelGGL(norm_finish_kernel, dim3((unsigned)a.nb), dim3(kFinThreads), 0, s, a.scratch, bpr, a.norms, a.skip);
   return hipGetLastError();
 }
 

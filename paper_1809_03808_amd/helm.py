@@ -31,6 +31,7 @@ EXPORTS = (
     "helm_default_options", "helm_setup", "helm_solve", "helm_report_get",
     "helm_residual", "helm_destroy", "helm_strerror", "helm_eig1d",
     "helm_profile", "helm_kernel_stats_get", "helm_kernel_name",
+    "helm_batch_create", "helm_batch_solve", "helm_batch_report_get", "helm_batch_destroy",
 )
 
 NKERNELS = 8
@@ -95,6 +96,14 @@ def lib():
     L.helm_kernel_stats_get.restype = ctypes.c_int
     L.helm_kernel_name.argtypes = [ctypes.c_int]
     L.helm_kernel_name.restype = ctypes.c_char_p
+    L.helm_batch_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int, ctypes.c_int, ctypes.POINTER(vp)]
+    L.helm_batch_create.restype = ctypes.c_int
+    L.helm_batch_solve.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(ctypes.c_int), vp]
+    L.helm_batch_solve.restype = ctypes.c_int
+    L.helm_batch_report_get.argtypes = [vp, ctypes.c_int, ctypes.POINTER(Report)]
+    L.helm_batch_report_get.restype = ctypes.c_int
+    L.helm_batch_destroy.argtypes = [vp]
+    L.helm_batch_destroy.restype = None
     _lib = L
     return L
 
@@ -229,6 +238,67 @@ class Plan:
         if getattr(self, "_p", None):
             lib().helm_destroy(self._p)
             self._p = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
+class Batch:
+    """Independent problems solved by one graph launch.
+
+    ``Batch(plans, max_nrhs)`` then ``batch.solve(fs, us)`` with one
+    (f, u) tensor pair per plan.  The plans stay owned by the caller and must
+    outlive the batch.
+    """
+
+    def __init__(self, plans, max_nrhs=1):
+        L = lib()
+        self.plans = list(plans)
+        arr = (ctypes.c_void_p * len(self.plans))(*[p._p.value for p in self.plans])
+        out = ctypes.c_void_p()
+        rc = L.helm_batch_create(arr, len(self.plans), int(max_nrhs), ctypes.byref(out))
+        if rc != HELM_OK:
+            raise HelmError(rc, "helm_batch_create")
+        self._b = out
+
+    def solve(self, fs, us, stream=None, raise_on_error=True):
+        n = len(self.plans)
+        if len(fs) != n or len(us) != n:
+            raise ValueError("one f and one u per plan")
+        nr = []
+        for p, f, u in zip(self.plans, fs, us):
+            k = _check_tensor(f, p.grid, "f")
+            if _check_tensor(u, p.grid, "u") != k:
+                raise ValueError("f and u hold different numbers of right-hand sides")
+            nr.append(k)
+        fa = (ctypes.c_void_p * n)(*[f.data_ptr() for f in fs])
+        ua = (ctypes.c_void_p * n)(*[u.data_ptr() for u in us])
+        na = (ctypes.c_int * n)(*nr)
+        rc = lib().helm_batch_solve(self._b, fa, ua, na, _stream_ptr(stream))
+        if rc != HELM_OK and raise_on_error:
+            raise HelmError(rc, "helm_batch_solve")
+        return rc
+
+    def report(self, i):
+        r = Report()
+        rc = lib().helm_batch_report_get(self._b, int(i), ctypes.byref(r))
+        if rc != HELM_OK:
+            raise HelmError(rc, "helm_batch_report_get")
+        return {k: getattr(r, k) for k, _ in Report._fields_}
+
+    def close(self):
+        if getattr(self, "_b", None):
+            lib().helm_batch_destroy(self._b)
+            self._b = None
 
     def __del__(self):
         try:

@@ -58,3 +58,15 @@ def test_setup_argument_errors(grid, h, omega, mask, code):
     with pytest.raises(helm.HelmError) as e:
         helm.Plan(grid, h, omega, mask)
     assert e.value.code == code
+
+
+def test_batch_create_rejects_bad_arguments():
+    import ctypes
+    L = helm.lib()
+    out = ctypes.c_void_p()
+    arr = (ctypes.c_void_p * 1)(None)
+    assert L.helm_batch_create(None, 1, 1, ctypes.byref(out)) == helm.HELM_EINVAL
+    assert L.helm_batch_create(arr, 0, 1, ctypes.byref(out)) == helm.HELM_EINVAL
+    assert L.helm_batch_create(arr, 1, 0, ctypes.byref(out)) == helm.HELM_EINVAL
+    assert L.helm_batch_solve(None, None, None, None, None) == helm.HELM_EINVAL
+    L.helm_batch_destroy(None)
