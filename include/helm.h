@@ -51,6 +51,21 @@ extern "C" {
 
 /* Solver options.  helm_default_options fills: precision = HELM_PREC_FP64,
  * tol = 1e-10, max_iter = 8, check = 1. */
+/* Transform along the periodised axes (helm_options.transform):
+ *   FFT   the fast method of Sections 4.2 / 5.2: DFTs of the periodic
+ *         problem, three line passes and the boundary steps;
+ *   DENSE diagonalisation with the full absorbing-boundary eigenvectors,
+ *         u = (V (x) I) T^{-1} (V^T (x) I) f (eq. (A2Dinv); 3D with V_1 (x) V_2):
+ *         two dense complex transforms on the matrix cores and one line pass;
+ *         periodised lengths up to HELM_DENSE_MAX;
+ *   AUTO  the plan times both at setup (one right-hand side, the plan's
+ *         precision) and keeps the faster; with tune_cache set, decisions are
+ *         read from and appended to that text file, keyed by the problem shape. */
+#define HELM_TRANSFORM_AUTO  0
+#define HELM_TRANSFORM_FFT   1
+#define HELM_TRANSFORM_DENSE 2
+#define HELM_DENSE_MAX 1024
+
 typedef struct helm_options {
     int    precision; /* HELM_PREC_FP64 or HELM_PREC_MIXED */
     double tol;       /* target ||f - A u||_2 / ||f||_2 per right-hand side */
@@ -58,6 +73,8 @@ typedef struct helm_options {
     int    check;     /* FP64 path: 1 = evaluate the FP64 residual after the solve and
                          refine while it exceeds tol; 0 = one plain solve, no residual.
                          The mixed path always checks. */
+    int    transform; /* HELM_TRANSFORM_*; default FFT */
+    const char* tune_cache; /* AUTO only: decision cache file, or NULL */
 } helm_options;
 
 void helm_default_options(helm_options* opt);
@@ -112,6 +129,7 @@ typedef struct helm_report {
     int    nrhs;
     double rel_residual_max;  /* max over RHS of ||f - A u|| / ||f|| (FP64), -1 if unchecked */
     double rel_residual_first;/* same after the first solve, -1 if unchecked */
+    int    transform;         /* HELM_TRANSFORM_FFT or _DENSE: the variant the plan runs */
 } helm_report;
 
 int helm_report_get(const helm_plan* p, helm_report* out);

@@ -184,9 +184,10 @@ void apply_mass(const XPencil& P, const std::vector<xc>& x, std::vector<xc>& y) 
 struct Refined {
   cd lam, v0, v1;
   double resid;
+  std::vector<cd> x;  // the whole eigenvector, when asked for
 };
 
-Refined refine(const XPencil& P, cd lam0, int steps) {
+Refined refine(const XPencil& P, cd lam0, int steps, bool whole) {
   const int n = P.n;
   std::vector<xc> x(n), y(n), dl(n), d(n), du(n), b(n);
   // Deterministic start vector with components of both parities.
@@ -219,15 +220,20 @@ Refined refine(const XPencil& P, cd lam0, int steps) {
   }
   const xr mnorm = 6.0L * P.mb;  // ||M||_inf = h
   const xr rden = (knorm + std::abs(lam) * mnorm) * xmax;
-  return Refined{cd((double)lam.real(), (double)lam.imag()), cd((double)x[0].real(), (double)x[0].imag()),
-                 cd((double)x[n - 1].real(), (double)x[n - 1].imag()),
-                 rden > 0 ? (double)(rnum / rden) : 0.0};
+  Refined out{cd((double)lam.real(), (double)lam.imag()), cd((double)x[0].real(), (double)x[0].imag()),
+              cd((double)x[n - 1].real(), (double)x[n - 1].imag()),
+              rden > 0 ? (double)(rnum / rden) : 0.0, {}};
+  if (whole) {
+    out.x.resize(n);
+    for (int i = 0; i < n; ++i) out.x[i] = cd((double)x[i].real(), (double)x[i].imag());
+  }
+  return out;
 }
 
 }  // namespace
 
 int eig1d(int n, double h, double omega, int lo, int hi, std::vector<cd>& lam_out,
-          std::vector<cd>& v0, std::vector<cd>& v1) {
+          std::vector<cd>& v0, std::vector<cd>& v1, std::vector<cd>* vfull) {
   if (n < 3 || !(h > 0.0) || !std::isfinite(omega)) return HELM_EINVAL;
   const Pencil P = make_pencil(n, h, omega, lo, hi);
   // Closed-form Neumann spectrum: exact when no face absorbs, the starting
@@ -281,7 +287,7 @@ int eig1d(int n, double h, double omega, int lo, int hi, std::vector<cd>& lam_ou
   double worst = 0.0;
 #pragma omp parallel for schedule(dynamic, 16) reduction(max : worst)
   for (int j = 0; j < n; ++j) {
-    R[j] = refine(XP, lam[j], 3);
+    R[j] = refine(XP, lam[j], 3, vfull != nullptr);
     worst = std::max(worst, R[j].resid);
   }
   if (!(worst < 1e-12)) return HELM_ENOCONV;
@@ -303,6 +309,11 @@ int eig1d(int n, double h, double omega, int lo, int hi, std::vector<cd>& lam_ou
     v0[j] = R[j].v0;
     v1[j] = R[j].v1;
   }
+  if (vfull) {
+    vfull->assign((size_t)n * n, cd(0.0));
+    for (int j = 0; j < n; ++j)
+      for (int i = 0; i < n; ++i) (*vfull)[(size_t)i * n + j] = R[j].x[i];
+  }
   return HELM_OK;
 }
 
@@ -314,7 +325,7 @@ extern "C" int helm_eig1d(int64_t n, double h, double omega, int abc_lo, int abc
   std::vector<helm::cd> L, V0, V1;
   int st;
   try {
-    st = helm::eig1d((int)n, h, omega, abc_lo, abc_hi, L, V0, V1);
+    st = helm::eig1d((int)n, h, omega, abc_lo, abc_hi, L, V0, V1, nullptr);
   } catch (...) {
     return HELM_ENOMEM;
   }

@@ -168,6 +168,26 @@ void lines_geometry(int nL, int* P, int* c, int* NT);
 hipError_t launch_line_factors(const LineArgs& a, double2* piv, hipStream_t s);
 
 // ---------------------------------------------------------------------------
+// Dense eigenvector transforms on the matrix cores (dense.hip)
+// ---------------------------------------------------------------------------
+// out[b][m][x] = scale * sum_i Q[i][m] in[b][i][x] (+ out[b][m][x] if
+// accumulate), b < batch, m, i < n, x < S; Q interleaved complex [n][n] in the
+// compute precision (double, or float when fp32).  in and out must not overlap.
+struct DenseArgs {
+  int n = 0;
+  int64_t S = 0, batch = 0;
+  const void* Q = nullptr;
+  const void* in = nullptr;
+  int in_kind = ST_C128;
+  void* out = nullptr;
+  int out_kind = ST_C128;
+  double scale = 1.0;
+  int accumulate = 0;
+  const int* skip = nullptr;
+};
+hipError_t launch_dense(const DenseArgs& a, bool fp32, hipStream_t s);
+
+// ---------------------------------------------------------------------------
 // Boundary kernels (boundary.hip)
 // ---------------------------------------------------------------------------
 // 2x2 boundary difference of a periodised axis (B - A restricted to its two

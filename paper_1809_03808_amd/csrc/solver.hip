@@ -17,6 +17,8 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <string>
+#include <cstdio>
 
 #include "helm_internal.h"
 
@@ -78,6 +80,10 @@ struct PAxis {
   const void* chirp_f[2] = {nullptr, nullptr};  // same in float2
   const void* bhat_d[2] = {nullptr, nullptr};   // FFT_M of the convolution kernel (double2[M])
   const void* bhat_f[2] = {nullptr, nullptr};
+  // full absorbing-boundary eigenvectors for the dense transform:
+  // V[i][l] = v_l(i) and its transpose, interleaved complex, double and float
+  DevMem vmat;
+  const void *Vd = nullptr, *VTd = nullptr, *Vf = nullptr, *VTf = nullptr;
 };
 
 }  // namespace
@@ -110,6 +116,9 @@ struct helm_plan {
   const double2* seed[4] = {nullptr, nullptr, nullptr, nullptr};
   // device-side refinement control (IrCtl) for captured solves
   helm::DevMem ctl;
+  int dense = 0;  // 1: periodised axes use the dense eigenvector transforms
+  std::string tune_path;
+  double tune_ms[2] = {-1.0, -1.0};  // measured FFT / dense solve times (AUTO)
   std::vector<double> h_norms;
   helm_report rep{};
   // per-kernel event timing
@@ -153,7 +162,9 @@ int map_err(hipError_t e) {
   } while (0)
 
 // Kernel slots of helm_kernel_stats.
-enum KSlot { K_FFT64 = 0, K_FFT32 = 1, K_LINES = 2, K_INNER_MID = 3, K_SUM = 4, K_OUTER_MID = 5, K_RESID = 6 };
+enum KSlot {
+  K_FFT64 = 0, K_FFT32 = 1, K_LINES = 2, K_INNER_MID = 3, K_SUM = 4, K_OUTER_MID = 5, K_RESID = 6, K_DENSE = 7
+};
 
 // Launch through `fn` (returning hipError_t), bracketed by events if profiling.
 template <class F> hipError_t timed(helm_plan* p, int cls, double bytes, hipStream_t st, F&& fn) {
@@ -621,9 +632,84 @@ int sum_to_planes(helm_plan* p, const Level& lv, double2* out, hipStream_t st) {
   return HELM_OK;
 }
 
+// Dense variant: u (+)= (V (x) I) T^{-1} (V^T (x) I) x (3D: V_1 (x) V_2), with
+// T the absorbing-boundary line matrices (sigma = lambda_A - w^2).
+int dense_pass(helm_plan* p, int n, int64_t S, int64_t batch, const void* Q, const void* in, int in_kind,
+               void* out, int out_kind, int accumulate, bool fp32, hipStream_t st) {
+  DenseArgs g;
+  g.n = n;
+  g.S = S;
+  g.batch = batch;
+  g.Q = Q;
+  g.in = in;
+  g.in_kind = in_kind;
+  g.out = out;
+  g.out_kind = out_kind;
+  g.accumulate = accumulate;
+  g.skip = p->skip_cur;
+  const double by = (double)batch * n * S * (esz_of(in_kind) + esz_of(out_kind) * (accumulate ? 2 : 1));
+  HCHK(timed(p, K_DENSE, by, st, [&] { return launch_dense(g, fp32, st); }));
+  return HELM_OK;
+}
+
+int solve_dense(helm_plan* p, const void* x, int x_kind, double2* u, int accumulate, int nb, bool fp32,
+                hipStream_t st) {
+  const int T = fp32 ? ST_C64 : ST_C128;
+  void* W0 = p->W0.p;
+  void* W1 = p->W1.p;
+  const PAxis& A1 = p->ax[0];
+  auto fwd = [&](const PAxis& A) { return fp32 ? A.Vf : A.Vd; };
+  auto inv = [&](const PAxis& A) { return fp32 ? A.VTf : A.VTd; };
+  LineArgs la;
+  la.nb = nb;
+  la.nL = p->nL;
+  la.sC = make_double2(-p->omega * p->omega, 0.0);
+  la.hL = p->hL;
+  la.kLo = p->kLo;
+  la.kHi = p->kHi;
+  la.skip = p->skip_cur;
+  la.in_kind = T;
+  la.out_kind = T;
+  int rc;
+  if (p->dim == 2) {
+    const int n1 = A1.n, n2 = p->nL;
+    rc = dense_pass(p, n1, n2, nb, fwd(A1), x, x_kind, W0, T, 0, fp32, st);
+    if (rc) return rc;
+    la.nO = 1;
+    la.nI = n1;
+    la.sI = A1.sigA;
+    la.piv = p->seed[1];
+    la.in = W0;
+    la.out = W0;
+    la.tile = 0;
+    tiles_for(0, nb, 1, n1, n2, &la.tile, &la.ntiles);
+    HCHK(timed(p, K_LINES, (double)nb * n1 * n2 * 2 * esz_of(T), st, [&] { return launch_lines(la, st); }));
+    return dense_pass(p, n1, n2, nb, inv(A1), W0, T, u, ST_C128, accumulate, fp32, st);
+  }
+  const PAxis& A2 = p->ax[1];
+  const int n1 = A1.n, n2 = A2.n, n3 = p->nL;
+  rc = dense_pass(p, n1, (int64_t)n2 * n3, nb, fwd(A1), x, x_kind, W0, T, 0, fp32, st);
+  if (rc) return rc;
+  rc = dense_pass(p, n2, n3, (int64_t)nb * n1, fwd(A2), W0, T, W1, T, 0, fp32, st);
+  if (rc) return rc;
+  la.nO = n1;
+  la.nI = n2;
+  la.sO = A1.sigA;
+  la.sI = A2.sigA;
+  la.piv = p->seed[3];
+  la.in = W1;
+  la.out = W1;
+  tiles_for(0, nb, n1, n2, n3, &la.tile, &la.ntiles);
+  HCHK(timed(p, K_LINES, (double)nb * n1 * n2 * n3 * 2 * esz_of(T), st, [&] { return launch_lines(la, st); }));
+  rc = dense_pass(p, n2, n3, (int64_t)nb * n1, inv(A2), W1, T, W0, T, 0, fp32, st);
+  if (rc) return rc;
+  return dense_pass(p, n1, (int64_t)n2 * n3, nb, inv(A1), W0, T, u, ST_C128, accumulate, fp32, st);
+}
+
 // Full solve of one precision pass: u (+)= A^{-1} x.
 int solve_once(helm_plan* p, const void* x, int x_kind, double2* u, int accumulate, int nb, bool fp32,
                hipStream_t st) {
+  if (p->dense) return solve_dense(p, x, x_kind, u, accumulate, nb, fp32, st);
   const int T = fp32 ? ST_C64 : ST_C128;
   const double w2 = p->omega * p->omega;
   void* W0 = p->W0.p;
@@ -855,6 +941,31 @@ int residual_norms(helm_plan* p, const double2* u, const double2* f, void* r, in
   return HELM_OK;
 }
 
+// Upload V[i][l] = v_l(i) and V^T, interleaved complex, in double and float.
+int upload_eigvecs(PAxis& a, const std::vector<cd>& v) {
+  const size_t n = (size_t)a.n, nn = n * n;
+  std::vector<double2> hd(2 * nn);
+  std::vector<float2> hf(2 * nn);
+  for (size_t i = 0; i < n; ++i)
+    for (size_t l = 0; l < n; ++l) {
+      const cd x = v[i * n + l];
+      hd[i * n + l] = make_double2(x.real(), x.imag());
+      hd[nn + l * n + i] = make_double2(x.real(), x.imag());
+    }
+  for (size_t k = 0; k < 2 * nn; ++k) hf[k] = make_float2((float)hd[k].x, (float)hd[k].y);
+  const size_t bd = 2 * nn * sizeof(double2), bf = 2 * nn * sizeof(float2);
+  if (a.vmat.ensure(bd + bf) != hipSuccess) return HELM_ENOMEM;
+  if (upload(a.vmat.p, hd.data(), bd) != hipSuccess) return HELM_EDEVICE;
+  if (upload((char*)a.vmat.p + bd, hf.data(), bf) != hipSuccess) return HELM_EDEVICE;
+  const double2* d = a.vmat.as<double2>();
+  const float2* f = reinterpret_cast<const float2*>((char*)a.vmat.p + bd);
+  a.Vd = d;
+  a.VTd = d + nn;
+  a.Vf = f;
+  a.VTf = f + nn;
+  return HELM_OK;
+}
+
 void fill_axis_tables_host(PAxis& a, double omega, std::vector<double2>& buf, std::vector<double>& invmu) {
   const int n = a.n;
   const double h = a.h;
@@ -990,6 +1101,95 @@ int enqueue_device_ir(helm_plan* p, const double2* F, double2* U, int nb, int st
 
 using namespace helm;
 
+// ---------------------------------------------------------------------------
+// Autotuner for the periodised-axis transform: times one solve of each
+// variant on the plan's own shape and precision (one right-hand side, after a
+// warm-up, best of three, HIP events) and keeps the faster.  Decisions can be
+// cached in a text file, one line per shape:
+//   helm-tune dim=<d> grid=<n1>x<n2>x<n3> prec=<p> transform=<t> fft_ms=<..> dense_ms=<..>
+// ---------------------------------------------------------------------------
+std::string tune_key(const helm_plan* p) {
+  char buf[160];
+  std::snprintf(buf, sizeof buf, "dim=%d grid=%lldx%lldx%lld prec=%d", p->dim, (long long)p->grid[0],
+                (long long)p->grid[1], (long long)(p->dim == 3 ? p->grid[2] : 1), p->opt.precision);
+  return buf;
+}
+
+bool tune_lookup(const std::string& path, const std::string& key, int* choice) {
+  FILE* f = std::fopen(path.c_str(), "r");
+  if (!f) return false;
+  const std::string pre = "helm-tune " + key + " transform=";
+  char line[512];
+  bool found = false;
+  while (std::fgets(line, sizeof line, f)) {
+    if (std::strncmp(line, pre.c_str(), pre.size()) != 0) continue;
+    const int t = std::atoi(line + pre.size());
+    if (t == HELM_TRANSFORM_FFT || t == HELM_TRANSFORM_DENSE) {
+      *choice = t;
+      found = true;  // the last matching line wins
+    }
+  }
+  std::fclose(f);
+  return found;
+}
+
+int autotune_transform(helm_plan* p) {
+  int choice = 0;
+  const std::string key = tune_key(p);
+  if (!p->tune_path.empty() && tune_lookup(p->tune_path, key, &choice)) {
+    p->dense = choice == HELM_TRANSFORM_DENSE;
+    return HELM_OK;
+  }
+  const bool fp32 = p->opt.precision == HELM_PREC_MIXED;
+  const int wrc = ensure_workspace(p, 1, fp32, false);
+  if (wrc != HELM_OK) return wrc;
+  const int64_t N = npoints(p);
+  DevMem tf, tu;
+  HCHK(tf.ensure((size_t)N * sizeof(double2)));
+  HCHK(tu.ensure((size_t)N * sizeof(double2)));
+  HCHK(hipMemset(tf.p, 0x3f, (size_t)N * sizeof(double2)));  // finite values of order 1e-3
+  hipEvent_t e0, e1;
+  HCHK(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return HELM_EDEVICE;
+  }
+  int rc = HELM_OK;
+  const bool prof = p->prof;
+  p->prof = false;
+  for (int cand = 0; cand < 2 && !rc; ++cand) {
+    p->dense = cand;
+    float best = 1e30f;
+    for (int rep = 0; rep < 4 && !rc; ++rep) {
+      if (hipEventRecord(e0, nullptr) != hipSuccess) { rc = HELM_EDEVICE; break; }
+      rc = solve_once(p, tf.p, ST_C128, tu.as<double2>(), 0, 1, fp32, nullptr);
+      if (rc) break;
+      if (hipEventRecord(e1, nullptr) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+        rc = HELM_EDEVICE;
+        break;
+      }
+      float ms = 0;
+      if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) { rc = HELM_EDEVICE; break; }
+      if (rep > 0) best = std::min(best, ms);  // rep 0 is the warm-up
+    }
+    p->tune_ms[cand] = best;
+  }
+  p->prof = prof;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc) return rc;
+  p->dense = p->tune_ms[1] < p->tune_ms[0] ? 1 : 0;
+  if (!p->tune_path.empty()) {
+    FILE* f = std::fopen(p->tune_path.c_str(), "a");
+    if (f) {
+      std::fprintf(f, "helm-tune %s transform=%d fft_ms=%.6g dense_ms=%.6g\n", key.c_str(),
+                   p->dense ? HELM_TRANSFORM_DENSE : HELM_TRANSFORM_FFT, p->tune_ms[0], p->tune_ms[1]);
+      std::fclose(f);
+    }
+  }
+  return HELM_OK;
+}
+
 // A batch of independent plans solved by one graph launch.  Each plan keeps
 // its own workspace; the plans' pipelines are spread over side streams
 // inside one stream capture (longest first onto the least loaded stream), so
@@ -1035,6 +1235,8 @@ void helm_default_options(helm_options* opt) {
   opt->tol = 1e-10;
   opt->max_iter = 8;
   opt->check = 1;
+  opt->transform = HELM_TRANSFORM_FFT;
+  opt->tune_cache = nullptr;
 }
 
 const char* helm_strerror(int code) {
@@ -1071,6 +1273,13 @@ int helm_setup(int dim, const int64_t* grid, const double* h, double omega, uint
   if (opt) p->opt = *opt;
   if (p->opt.precision != HELM_PREC_FP64 && p->opt.precision != HELM_PREC_MIXED) return HELM_EINVAL;
   if (p->opt.max_iter < 0 || !(p->opt.tol >= 0.0)) return HELM_EINVAL;
+  const int tf = p->opt.transform;
+  if (tf != HELM_TRANSFORM_AUTO && tf != HELM_TRANSFORM_FFT && tf != HELM_TRANSFORM_DENSE) return HELM_EINVAL;
+  if (p->opt.tune_cache) p->tune_path = p->opt.tune_cache;
+  p->opt.tune_cache = nullptr;
+  bool dense_ok = tf != HELM_TRANSFORM_FFT;
+  for (int j = 0; j < dim - 1; ++j) dense_ok = dense_ok && grid[j] <= HELM_DENSE_MAX;
+  if (tf == HELM_TRANSFORM_DENSE && !dense_ok) return HELM_EUNSUPPORTED;
   for (int j = 0; j < dim; ++j) {
     p->grid[j] = grid[j];
     p->h[j] = h[j];
@@ -1095,8 +1304,13 @@ int helm_setup(int dim, const int64_t* grid, const double* h, double omega, uint
       const int bst = setup_bluestein(a);
       if (bst != HELM_OK) return bst;
     }
-    const int st = eig1d(a.n, a.h, omega, a.lo, a.hi, a.lamA, a.va0, a.va1);
+    std::vector<cd> vfull;
+    const int st = eig1d(a.n, a.h, omega, a.lo, a.hi, a.lamA, a.va0, a.va1, dense_ok ? &vfull : nullptr);
     if (st != HELM_OK) return st;
+    if (dense_ok) {
+      const int ast = upload_eigvecs(a, vfull);
+      if (ast != HELM_OK) return ast;
+    }
     std::vector<double2> buf;
     std::vector<double> invmu;
     fill_axis_tables_host(a, omega, buf, invmu);
@@ -1146,6 +1360,12 @@ int helm_setup(int dim, const int64_t* grid, const double* h, double omega, uint
     }
     if (hipDeviceSynchronize() != hipSuccess) return HELM_EDEVICE;
   }
+  if (tf == HELM_TRANSFORM_DENSE) {
+    p->dense = 1;
+  } else if (tf == HELM_TRANSFORM_AUTO && dense_ok) {
+    const int trc = autotune_transform(p.get());
+    if (trc != HELM_OK) return trc;
+  }
   p->rep.status = HELM_OK;
   p->rep.rel_residual_max = -1;
   p->rep.rel_residual_first = -1;
@@ -1162,6 +1382,7 @@ int helm_solve(helm_plan* p, const void* f, void* u, int nrhs, void* stream) {
   helm_report& rep = p->rep;
   rep = helm_report{};
   rep.precision = p->opt.precision;
+  rep.transform = p->dense ? HELM_TRANSFORM_DENSE : HELM_TRANSFORM_FFT;
   rep.nrhs = nrhs;
   rep.rel_residual_max = -1;
   rep.rel_residual_first = -1;
@@ -1240,7 +1461,7 @@ int helm_kernel_stats_get(helm_plan* p, helm_kernel_stats* out, int reset) {
 const char* helm_kernel_name(int k) {
   static const char* names[HELM_NKERNELS] = {
       "fft_pass_kernel<double2>", "fft_pass_kernel<float2>", "lines_kernel", "inner_mid_kernel",
-      "sum_to_planes_kernel",     "outer_mid_kernel",        "residual_kernel", nullptr};
+      "sum_to_planes_kernel",     "outer_mid_kernel",        "residual_kernel", "dense_kernel"};
   return (k >= 0 && k < HELM_NKERNELS) ? names[k] : nullptr;
 }
 
@@ -1371,6 +1592,7 @@ int helm_batch_report_get(helm_batch* b, int i, helm_report* out) {
   r.status = c.status;
   r.iterations = c.iters;
   r.precision = p->opt.precision;
+  r.transform = p->dense ? HELM_TRANSFORM_DENSE : HELM_TRANSFORM_FFT;
   r.nrhs = b->kn[i];
   r.rel_residual_max = c.rel_last;
   r.rel_residual_first = c.rel_first;

@@ -25,6 +25,10 @@ HELM_EUNSUPPORTED = -7
 
 PREC_FP64 = 0
 PREC_MIXED = 1
+TRANSFORM_AUTO = 0
+TRANSFORM_FFT = 1
+TRANSFORM_DENSE = 2
+DENSE_MAX = 1024
 
 # Every symbol declared in include/helm.h.
 EXPORTS = (
@@ -39,14 +43,16 @@ NKERNELS = 8
 
 class Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("tol", ctypes.c_double),
-                ("max_iter", ctypes.c_int), ("check", ctypes.c_int)]
+                ("max_iter", ctypes.c_int), ("check", ctypes.c_int),
+                ("transform", ctypes.c_int), ("tune_cache", ctypes.c_char_p)]
 
 
 class Report(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int), ("iterations", ctypes.c_int),
                 ("precision", ctypes.c_int), ("nrhs", ctypes.c_int),
                 ("rel_residual_max", ctypes.c_double),
-                ("rel_residual_first", ctypes.c_double)]
+                ("rel_residual_first", ctypes.c_double),
+                ("transform", ctypes.c_int)]
 
 
 class KernelStats(ctypes.Structure):
@@ -157,7 +163,7 @@ class Plan:
     """A solver plan: ``Plan(grid, h, omega, abc)`` then ``plan.solve(f, u)``."""
 
     def __init__(self, grid, h, omega, abc=None, precision=PREC_FP64, tol=1e-10, max_iter=8,
-                 check=True):
+                 check=True, transform=None, tune_cache=None):
         L = lib()
         self.grid = tuple(int(n) for n in grid)
         self.dim = len(self.grid)
@@ -172,6 +178,10 @@ class Plan:
         opt.tol = float(tol)
         opt.max_iter = int(max_iter)
         opt.check = int(bool(check))
+        if transform is not None:
+            opt.transform = int(transform)
+        self._tune = tune_cache.encode() if tune_cache else None
+        opt.tune_cache = self._tune
         g = (ctypes.c_int64 * self.dim)(*self.grid)
         hh = (ctypes.c_double * self.dim)(*self.h)
         out = ctypes.c_void_p()

@@ -70,3 +70,15 @@ def test_batch_create_rejects_bad_arguments():
     assert L.helm_batch_create(arr, 1, 0, ctypes.byref(out)) == helm.HELM_EINVAL
     assert L.helm_batch_solve(None, None, None, None, None) == helm.HELM_EINVAL
     L.helm_batch_destroy(None)
+
+
+def test_dense_transform_size_limit():
+    """DENSE needs every periodised length <= HELM_DENSE_MAX (checked before
+    any device call); an unknown transform code is rejected."""
+    n = helm.DENSE_MAX + 1
+    with pytest.raises(helm.HelmError) as e:
+        helm.Plan((n, 16), (1.0 / (n - 1), 1 / 15), 5.0, transform=helm.TRANSFORM_DENSE)
+    assert e.value.code == helm.HELM_EUNSUPPORTED
+    with pytest.raises(helm.HelmError) as e:
+        helm.Plan((16, 16), (1 / 15, 1 / 15), 5.0, transform=7)
+    assert e.value.code == helm.HELM_EINVAL

@@ -1,0 +1,128 @@
+"""The dense variant (diagonalisation with the full absorbing-boundary
+eigenvectors on the matrix cores, eq. (A2Dinv)) and the transform autotuner,
+through the C ABI, against the CPU oracle: FP64 relative error <= 1e-9,
+mixed precision relative residual <= 1e-10 with error <= 1e-8."""
+
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import fem
+from paper_1809_03808_amd import helm, inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def _abc_tuple(dim, mask):
+    return tuple(((mask >> (2 * j)) & 1 == 1, (mask >> (2 * j + 1)) & 1 == 1) for j in range(dim))
+
+
+def _solve(grid, omega, mask, f, precision, transform, tune_cache=None):
+    h = inputs.spacing(grid)
+    _say("case", grid, omega, bin(mask), "prec", precision, "transform", transform, "nrhs", f.shape[0])
+    with helm.Plan(grid, h, omega, mask, precision=precision, transform=transform,
+                   tune_cache=tune_cache) as plan:
+        fd = torch.from_numpy(f).cuda()
+        ud = torch.empty_like(fd)
+        rc = plan.solve(fd, ud, raise_on_error=False)
+        torch.cuda.synchronize()
+        rep = plan.report()
+        u = ud.cpu().numpy()
+    return rc, rep, u, h
+
+
+CASES = [
+    ((16, 13), 10.0, 0b1111),
+    ((33, 20), 15.0, 0b1111),
+    ((64, 100), 40.0, 0b1111),
+    ((100, 31), 30.0, 0b1100),   # x1 both Neumann
+    ((64, 41), 30.0, 0b0110),    # mixed faces on both axes
+    ((257, 65), 80.0, 0b1111),
+    ((8, 8, 9), 6.0, 0b111111),
+    ((12, 10, 9), 8.0, 0b111111),
+    ((16, 8, 13), 12.0, 0b111111),
+    ((8, 16, 7), 10.0, 0b110111),
+]
+
+
+@pytest.mark.parametrize("grid,omega,mask", CASES)
+def test_dense_fp64_matches_banded_lu(grid, omega, mask):
+    f = inputs.gaussian_batch(grid, [71, 72])
+    rc, rep, u, h = _solve(grid, omega, mask, f, helm.PREC_FP64, helm.TRANSFORM_DENSE)
+    ref = fem.solve(grid, h, omega, _abc_tuple(len(grid), mask), f.reshape(2, -1))
+    err = fem.rel_error(u.reshape(2, -1), ref)
+    _say("  rel err", err, rep)
+    assert rc == helm.HELM_OK and rep["transform"] == helm.TRANSFORM_DENSE
+    assert np.max(err) <= 1e-9
+
+
+@pytest.mark.parametrize("grid,omega", [((64, 77), 35.0), ((12, 20, 9), 12.0), ((257, 33), 90.0)])
+def test_dense_mixed_refines_to_1e10(grid, omega):
+    mask = (1 << (2 * len(grid))) - 1
+    f = inputs.gaussian_batch(grid, [81, 82, 83])
+    rc, rep, u, h = _solve(grid, omega, mask, f, helm.PREC_MIXED, helm.TRANSFORM_DENSE)
+    abc = _abc_tuple(len(grid), mask)
+    ref = fem.solve(grid, h, omega, abc, f.reshape(3, -1))
+    err = fem.rel_error(u.reshape(3, -1), ref)
+    res = fem.rel_residual(grid, h, omega, abc, u.reshape(3, -1), f.reshape(3, -1))
+    _say("  mixed dense err", err, "res", res, rep)
+    assert rc == helm.HELM_OK
+    assert np.max(res) <= 1e-10 and np.max(err) <= 1e-8
+
+
+def test_autotuner_decides_and_caches(tmp_path):
+    path = str(tmp_path / "tune.txt")
+    grid, omega = (48, 40), 25.0
+    f = inputs.gaussian_batch(grid, [91])
+    rc, rep, u, h = _solve(grid, omega, 0b1111, f, helm.PREC_FP64, helm.TRANSFORM_AUTO, path)
+    assert rc == helm.HELM_OK and rep["transform"] in (helm.TRANSFORM_FFT, helm.TRANSFORM_DENSE)
+    ref = fem.solve(grid, h, omega, _abc_tuple(2, 0b1111), f.reshape(1, -1))
+    assert fem.rel_error(u.reshape(1, -1), ref)[0] <= 1e-9
+    lines = open(path).read().splitlines()
+    _say("  tune cache:", lines)
+    assert len(lines) == 1 and lines[0].startswith("helm-tune dim=2 grid=48x40x1 prec=0 transform=")
+    # a second plan of the same shape takes the cached decision without timing
+    rc2, rep2, u2, _ = _solve(grid, 60.0, 0b1111, f, helm.PREC_FP64, helm.TRANSFORM_AUTO, path)
+    assert rc2 == helm.HELM_OK and rep2["transform"] == rep["transform"]
+    assert len(open(path).read().splitlines()) == 1
+    # a forced choice in the cache is honoured
+    forced = helm.TRANSFORM_DENSE if rep["transform"] == helm.TRANSFORM_FFT else helm.TRANSFORM_FFT
+    with open(path, "a") as fh:
+        fh.write(lines[0].split(" transform=")[0] + f" transform={forced} fft_ms=0 dense_ms=0\n")
+    rc3, rep3, u3, _ = _solve(grid, omega, 0b1111, f, helm.PREC_FP64, helm.TRANSFORM_AUTO, path)
+    assert rc3 == helm.HELM_OK and rep3["transform"] == forced
+    assert fem.rel_error(u3.reshape(1, -1), ref)[0] <= 1e-9
+
+
+def test_batch_of_dense_and_fft_plans():
+    probs = [((40, 33), 20.0, helm.TRANSFORM_DENSE), ((40, 33), 20.0, helm.TRANSFORM_FFT),
+             ((12, 10, 9), 8.0, helm.TRANSFORM_DENSE)]
+    plans, fs, us, hosts = [], [], [], []
+    for i, (grid, omega, tf) in enumerate(probs):
+        plans.append(helm.Plan(grid, inputs.spacing(grid), omega, precision=helm.PREC_MIXED, transform=tf))
+        f = inputs.gaussian_batch(grid, [inputs.rhs_seed(6, i, r) for r in range(2)])
+        hosts.append(f)
+        fs.append(torch.from_numpy(f).cuda())
+        us.append(torch.empty_like(fs[-1]))
+    batch = helm.Batch(plans, max_nrhs=2)
+    for launch in range(2):
+        batch.solve(fs, us)
+        for i, (grid, omega, tf) in enumerate(probs):
+            rep = batch.report(i)
+            u = us[i].cpu().numpy().reshape(2, -1)
+            abc = _abc_tuple(len(grid), (1 << (2 * len(grid))) - 1)
+            res = fem.rel_residual(grid, inputs.spacing(grid), omega, abc, u, hosts[i].reshape(2, -1))
+            _say(f"  launch {launch} problem {i}: res {res} {rep}")
+            assert rep["status"] == helm.HELM_OK and rep["transform"] == tf
+            assert np.max(res) <= 1e-10
+    batch.close()
+    for p in plans:
+        p.close()
