@@ -107,12 +107,15 @@ def batch_leg(steps, warmup, count=64):
     with eager helm_solve calls on one stream."""
     import torch
     from paper_1809_03808_amd import helm, inputs
+    import tempfile
     probs = inputs.batched_2d_problems(count=count, seed=4000)
+    tune = os.path.join(tempfile.mkdtemp(prefix="helm_tune_"), "tune.txt")
     t0 = time.perf_counter()
     plans, fs, us = [], [], []
     for i, pr in enumerate(probs):
         g = pr["grid"]
-        plans.append(helm.Plan(g, inputs.spacing(g), pr["omega"], precision=helm.PREC_MIXED))
+        plans.append(helm.Plan(g, inputs.spacing(g), pr["omega"], precision=helm.PREC_MIXED,
+                               transform=helm.TRANSFORM_AUTO, tune_cache=tune))
         fs.append(inputs.gaussian_device(g, [inputs.rhs_seed(4, i, r) for r in range(pr["nrhs"])], "cuda"))
         us.append(torch.empty_like(fs[-1]))
     setup_s = time.perf_counter() - t0
@@ -131,6 +134,12 @@ def batch_leg(steps, warmup, count=64):
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1e3 / steps
     reps = [batch.report(i) for i in range(len(plans))]
+    chosen = {}
+    for pr, r in zip(probs, reps):
+        key = f"{pr['grid'][0]}:{'dense' if r['transform'] == helm.TRANSFORM_DENSE else 'fft'}"
+        chosen[key] = chosen.get(key, 0) + 1
+    with open(tune) as fh:
+        tune_lines = [ln.strip() for ln in fh if ln.strip()]
     # eager reference: the same solves one after another on one stream
     t0 = time.perf_counter()
     for p, f, u in zip(plans, fs, us):
@@ -152,6 +161,7 @@ def batch_leg(steps, warmup, count=64):
             "rel_residual_max": max(r["rel_residual_max"] for r in reps),
             "refinement_steps_max": max(r["iterations"] for r in reps),
             "eager_sequential_ms": round(eager_ms, 3), "graph_speedup_vs_eager": round(eager_ms / ms, 3),
+            "transform_chosen": chosen, "tuner_decisions": tune_lines,
             "setup_s": round(setup_s, 2), "first_call_s": round(first_s, 2)}
 
 
