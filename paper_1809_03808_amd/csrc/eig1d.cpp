@@ -185,6 +185,7 @@ struct Refined {
   cd lam, v0, v1;
   double resid;
   std::vector<cd> x;  // the whole eigenvector, when asked for
+  cd lam_lo;          // extended-precision eigenvalue minus lam (rounded)
 };
 
 Refined refine(const XPencil& P, cd lam0, int steps, bool whole) {
@@ -220,9 +221,11 @@ Refined refine(const XPencil& P, cd lam0, int steps, bool whole) {
   }
   const xr mnorm = 6.0L * P.mb;  // ||M||_inf = h
   const xr rden = (knorm + std::abs(lam) * mnorm) * xmax;
-  Refined out{cd((double)lam.real(), (double)lam.imag()), cd((double)x[0].real(), (double)x[0].imag()),
+  const cd lhi((double)lam.real(), (double)lam.imag());
+  Refined out{lhi, cd((double)x[0].real(), (double)x[0].imag()),
               cd((double)x[n - 1].real(), (double)x[n - 1].imag()),
-              rden > 0 ? (double)(rnum / rden) : 0.0, {}};
+              rden > 0 ? (double)(rnum / rden) : 0.0, {},
+              cd((double)(lam.real() - (xr)lhi.real()), (double)(lam.imag() - (xr)lhi.imag()))};
   if (whole) {
     out.x.resize(n);
     for (int i = 0; i < n; ++i) out.x[i] = cd((double)x[i].real(), (double)x[i].imag());
@@ -233,7 +236,7 @@ Refined refine(const XPencil& P, cd lam0, int steps, bool whole) {
 }  // namespace
 
 int eig1d(int n, double h, double omega, int lo, int hi, std::vector<cd>& lam_out,
-          std::vector<cd>& v0, std::vector<cd>& v1, std::vector<cd>* vfull) {
+          std::vector<cd>& v0, std::vector<cd>& v1, std::vector<cd>* vfull, std::vector<cd>* lam_lo) {
   if (n < 3 || !(h > 0.0) || !std::isfinite(omega)) return HELM_EINVAL;
   const Pencil P = make_pencil(n, h, omega, lo, hi);
   // Closed-form Neumann spectrum: exact when no face absorbs, the starting
@@ -309,6 +312,10 @@ int eig1d(int n, double h, double omega, int lo, int hi, std::vector<cd>& lam_ou
     v0[j] = R[j].v0;
     v1[j] = R[j].v1;
   }
+  if (lam_lo) {
+    lam_lo->resize(n);
+    for (int j = 0; j < n; ++j) (*lam_lo)[j] = R[j].lam_lo;
+  }
   if (vfull) {
     vfull->assign((size_t)n * n, cd(0.0));
     for (int j = 0; j < n; ++j)
@@ -325,7 +332,7 @@ extern "C" int helm_eig1d(int64_t n, double h, double omega, int abc_lo, int abc
   std::vector<helm::cd> L, V0, V1;
   int st;
   try {
-    st = helm::eig1d((int)n, h, omega, abc_lo, abc_hi, L, V0, V1, nullptr);
+    st = helm::eig1d((int)n, h, omega, abc_lo, abc_hi, L, V0, V1, nullptr, nullptr);
   } catch (...) {
     return HELM_ENOMEM;
   }

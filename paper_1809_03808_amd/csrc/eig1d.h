@@ -9,10 +9,12 @@ namespace helm {
 // All eigenpairs of K v = lambda M v for the 1D matrices of eqs. (matrixK),
 // (matrixM) on n nodes with mesh size h; lo/hi = 1 for an absorbing face.
 // Eigenvectors are normalised v^T M v = 1; v0[l] = v_l(0), v1[l] = v_l(n-1),
-// and, if vfull is given, (*vfull)[i n + l] = v_l(i) (n x n, row-major).
-// Returns a HELM_* status.
+// and, if vfull is given, (*vfull)[i n + l] = v_l(i) (n x n, row-major).  If
+// lam_lo is given, lam[l] + lam_lo[l] is the eigenvalue to extended precision
+// (the refinement runs in long double).  Returns a HELM_* status.
 int eig1d(int n, double h, double omega, int lo, int hi, std::vector<std::complex<double>>& lam,
           std::vector<std::complex<double>>& v0, std::vector<std::complex<double>>& v1,
-          std::vector<std::complex<double>>* vfull = nullptr);
+          std::vector<std::complex<double>>* vfull = nullptr,
+          std::vector<std::complex<double>>* lam_lo = nullptr);
 
 }  // namespace helm

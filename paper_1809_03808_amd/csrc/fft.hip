@@ -18,7 +18,14 @@ namespace helm {
 namespace {
 
 constexpr int kFftThreads = 256;
-constexpr int kFftLdsBytes = 64 * 1024;
+#ifndef HELM_FFT_TILE_BYTES
+#define HELM_FFT_TILE_BYTES 32768
+#endif
+#ifndef HELM_FFT_MAX_W
+#define HELM_FFT_MAX_W 32
+#endif
+constexpr int kFftLdsBytes = HELM_FFT_TILE_BYTES;
+constexpr int kFftMaxW = HELM_FFT_MAX_W;
 
 template <typename C> struct RealOf;
 template <> struct RealOf<double2> { using T = double; };
@@ -129,6 +136,10 @@ struct PassDev {
   int sign, acc, in_kind, out_kind;
   const void* cmode;
   const int* skip;
+  const void* cin;
+  const void* cout;
+  int64_t chirp_n, chirp_na, chirp_S;
+  int tw4_mode, conj_out;
   int64_t I, od, in_so, in_sj, out_so1, out_so2, out_sk, tw4_S;
   int64_t ntile;  // tiles along I
   double scale_c;
@@ -144,9 +155,10 @@ constexpr int nstages(int L) { return ilog2(L) / 3 + (ilog2(L) % 3 ? 1 : 0); }
 constexpr int radix_of(int L, int s) {
   return (ilog2(L) % 3 && s == 0) ? (ilog2(L) % 3 == 1 ? 2 : 4) : 8;
 }
-// Columns per tile: a 64 KB LDS tile of L x W complex values, W <= 64.
+// Columns per tile: an LDS tile of L x W complex values (at most kFftLdsBytes),
+// W <= kFftMaxW.  32 KB tiles keep several blocks resident per compute unit.
 template <typename C> constexpr int tile_w(int L) {
-  return (65536 / (L * (int)sizeof(C))) < 64 ? 65536 / (L * (int)sizeof(C)) : 64;
+  return (kFftLdsBytes / (L * (int)sizeof(C))) < kFftMaxW ? kFftLdsBytes / (L * (int)sizeof(C)) : kFftMaxW;
 }
 
 // One Stockham stage of radix R with Ns points already combined.  Thread
@@ -155,9 +167,11 @@ template <typename C> constexpr int tile_w(int L) {
 // barrier and all writes follow it, so the stage works in place in LDS.  The
 // first stage reads global memory, the last writes it (with the four-step
 // twiddle, the per-mode scale and the optional accumulation).
-template <int L, int W, int R, int Ns, bool FIRST, bool LAST, typename C>
+template <int L, int W, int R, int Ns, bool FIRST, bool LAST, typename C, bool GIN = true, bool GOUT = true>
 __device__ inline void stage(const PassDev& p, C* sm, const void* in, void* out, int64_t o, int64_t i0,
                              int64_t oq, int64_t orr, int64_t a4) {
+  constexpr bool LOADG = FIRST && GIN;    // this stage reads global memory
+  constexpr bool STOREG = LAST && GOUT;   // this stage writes global memory
   constexpr int LR = L / R;
   constexpr int NBF = LR * W;
   constexpr int NB = (NBF + kFftThreads - 1) / kFftThreads;
@@ -175,10 +189,18 @@ __device__ inline void stage(const PassDev& p, C* sm, const void* in, void* out,
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         const int row = j + r * LR;
-        if constexpr (FIRST) {
+        if constexpr (LOADG) {
           C x;
-          if (colok) x = load_as<C>(in, o * p.in_so + (int64_t)row * p.in_sj + col, p.in_kind);
-          else { x.x = 0; x.y = 0; }
+          x.x = 0;
+          x.y = 0;
+          if (p.cin) {
+            const int64_t xr = col / p.chirp_S + p.chirp_na * row;
+            if (colok && xr < p.chirp_n)
+              x = cmul(load_as<C>(in, o * p.in_so + (int64_t)row * p.in_sj + col, p.in_kind),
+                       reinterpret_cast<const C*>(p.cin)[xr]);
+          } else if (colok) {
+            x = load_as<C>(in, o * p.in_so + (int64_t)row * p.in_sj + col, p.in_kind);
+          }
           v[q][r] = x;
         } else {
           v[q][r] = sm[row * W + w];
@@ -186,7 +208,7 @@ __device__ inline void stage(const PassDev& p, C* sm, const void* in, void* out,
       }
     }
   }
-  if constexpr (!FIRST) __syncthreads();
+  if constexpr (!LOADG) __syncthreads();
 #pragma unroll
   for (int q = 0; q < NB; ++q) {
     const int t = tid + q * kFftThreads;
@@ -200,7 +222,7 @@ __device__ inline void stage(const PassDev& p, C* sm, const void* in, void* out,
       }
       dft<R, C>(v[q], p.sign);
       const int base = (j / Ns) * Ns * R + k;
-      if constexpr (!LAST) {
+      if constexpr (!STOREG) {
 #pragma unroll
         for (int r = 0; r < R; ++r) sm[(base + r * Ns) * W + w] = v[q][r];
       } else {
@@ -208,15 +230,24 @@ __device__ inline void stage(const PassDev& p, C* sm, const void* in, void* out,
 #pragma unroll
           for (int r = 0; r < R; ++r) {
             const int kk = base + r * Ns;  // output frequency of this pass
-            C y = v[q][r];
-            if (p.tw4) {
-              // kk < L and a4 < n / L, so kk * a4 < n: no reduction needed
-              const C* t4 = reinterpret_cast<const C*>(p.tw4);
-              y = cmul(y, t4[kk * a4]);
+            // mode index of the per-mode factors: the chirp row map when
+            // folding a chirp, else the pass's own output index
+            int64_t mi = orr + p.od * kk;
+            if (p.cout) {
+              mi = col / p.chirp_S + p.chirp_na * kk;
+              if (mi >= p.chirp_n) continue;  // rows past the transform length are not stored
             }
-            if (p.cmode) y = cmul(y, reinterpret_cast<const C*>(p.cmode)[orr + p.od * kk]);
+            C y = v[q][r];
+            if (p.conj_out) y.y = -y.y;
+            if (p.tw4) {
+              // kk < L and the multiplier < n / L, so the index stays below n
+              const C* t4 = reinterpret_cast<const C*>(p.tw4);
+              y = cmul(y, t4[kk * (p.tw4_mode ? orr : a4)]);
+            }
+            if (p.cmode) y = cmul(y, reinterpret_cast<const C*>(p.cmode)[mi]);
+            if (p.cout) y = cmul(y, reinterpret_cast<const C*>(p.cout)[mi]);
             double s = p.scale_c;
-            if (p.scale) s *= p.scale[orr + p.od * kk];
+            if (p.scale) s *= p.scale[mi];
             y.x = (typename RealOf<C>::T)(y.x * s);
             y.y = (typename RealOf<C>::T)(y.y * s);
             store_as<C>(out, oq * p.out_so1 + orr * p.out_so2 + kk * p.out_sk + col, p.out_kind, y, p.acc);
@@ -225,16 +256,16 @@ __device__ inline void stage(const PassDev& p, C* sm, const void* in, void* out,
       }
     }
   }
-  if constexpr (!LAST) __syncthreads();
+  if constexpr (!STOREG) __syncthreads();
 }
 
-template <int L, int W, int S, int Ns, typename C>
+template <int L, int W, int S, int Ns, typename C, bool GIN = true, bool GOUT = true>
 __device__ inline void stages(const PassDev& p, C* sm, const void* in, void* out, int64_t o, int64_t i0,
                               int64_t oq, int64_t orr, int64_t a4) {
   if constexpr (S < nstages(L)) {
     constexpr int R = radix_of(L, S);
-    stage<L, W, R, Ns, S == 0, S == nstages(L) - 1, C>(p, sm, in, out, o, i0, oq, orr, a4);
-    stages<L, W, S + 1, Ns * R, C>(p, sm, in, out, o, i0, oq, orr, a4);
+    stage<L, W, R, Ns, S == 0, S == nstages(L) - 1, C, GIN, GOUT>(p, sm, in, out, o, i0, oq, orr, a4);
+    stages<L, W, S + 1, Ns * R, C, GIN, GOUT>(p, sm, in, out, o, i0, oq, orr, a4);
   }
 }
 
@@ -249,6 +280,61 @@ __global__ __launch_bounds__(kFftThreads) void fft_pass_kernel(PassDev p, const 
   const int64_t oq = o / p.od, orr = o - oq * p.od;
   const int64_t a4 = p.tw4 ? (i0 + (int64_t)(threadIdx.x % W)) / p.tw4_S : 0;
   stages<L, W, 0, 1, C>(p, sm, in, out, o, i0, oq, orr, a4);
+}
+
+// Chirp-z middle pass: forward DFT over the rows into LDS, multiplication by
+// the transformed kernel, conjugation, a second forward DFT, and the
+// conjugating epilogue: conj(DFT(conj(X))) is the unscaled inverse DFT.
+template <int L, typename C>
+__global__ __launch_bounds__(kFftThreads) void conv_pass_kernel(PassDev p, const void* in, void* out) {
+  constexpr int W = tile_w<C>(L);
+  __shared__ C sm[L * W];
+  if (p.skip && *p.skip) return;
+  const int64_t blk = blockIdx.x;
+  const int64_t o = blk / p.ntile;
+  const int64_t i0 = (blk - o * p.ntile) * W;
+  const int64_t oq = o / p.od, orr = o - oq * p.od;
+  stages<L, W, 0, 1, C, true, false>(p, sm, in, out, o, i0, oq, orr, 0);
+  const C* hk = reinterpret_cast<const C*>(p.cmode);
+  for (int e = threadIdx.x; e < L * W; e += kFftThreads) {
+    const int d = e / W;
+    C y = cmul(sm[e], hk[orr + p.od * d]);
+    y.y = -y.y;
+    sm[e] = y;
+  }
+  __syncthreads();
+  PassDev q = p;
+  q.cmode = nullptr;
+  q.cin = nullptr;
+  stages<L, W, 0, 1, C, false, true>(q, sm, in, out, o, i0, oq, orr, 0);
+}
+
+template <int L, typename C>
+hipError_t launch_conv_L(const PassDev& p, int64_t O, const void* in, void* out, hipStream_t s) {
+  constexpr int W = tile_w<C>(L);
+  PassDev q = p;
+  q.ntile = (p.I + W - 1) / W;
+  const int64_t blocks = O * q.ntile;
+  if (blocks <= 0) return hipSuccess;
+  if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((conv_pass_kernel<L, C>), dim3((unsigned)blocks), dim3(kFftThreads), 0, s, q, in, out);
+  return hipGetLastError();
+}
+
+template <typename C>
+hipError_t launch_conv_typed(int L, const PassDev& p, int64_t O, const void* in, void* out, hipStream_t s) {
+  switch (L) {
+    case 2: return launch_conv_L<2, C>(p, O, in, out, s);
+    case 4: return launch_conv_L<4, C>(p, O, in, out, s);
+    case 8: return launch_conv_L<8, C>(p, O, in, out, s);
+    case 16: return launch_conv_L<16, C>(p, O, in, out, s);
+    case 32: return launch_conv_L<32, C>(p, O, in, out, s);
+    case 64: return launch_conv_L<64, C>(p, O, in, out, s);
+    case 128: return launch_conv_L<128, C>(p, O, in, out, s);
+    case 256: return launch_conv_L<256, C>(p, O, in, out, s);
+    case 512: return launch_conv_L<512, C>(p, O, in, out, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 template <int L, typename C>
@@ -279,47 +365,11 @@ hipError_t launch_typed(int L, const PassDev& p, int64_t O, const void* in, void
   }
 }
 
-template <typename C>
-__global__ __launch_bounds__(256) void chirp_kernel(ChirpArgs a, const void* in, void* out, int64_t nib) {
-  if (a.skip && *a.skip) return;
-  const int64_t o = blockIdx.y;
-  const int64_t k = blockIdx.x / nib;
-  const int64_t i = (blockIdx.x - k * nib) * 256 + threadIdx.x;
-  if (i >= a.S) return;
-  const C w = reinterpret_cast<const C*>(a.w)[k < a.n ? k : 0];
-  if (!a.post) {
-    C v;
-    if (k < a.n) v = cmul(load_as<C>(in, (o * a.n + k) * a.S + i, a.in_kind), w);
-    else { v.x = 0; v.y = 0; }
-    store_as<C>(out, (o * a.M + k) * a.S + i, a.out_kind, v, 0);
-  } else {
-    C v = cmul(load_as<C>(in, (o * a.M + k) * a.S + i, a.in_kind), w);
-    double s = a.scale_c;
-    if (a.scale) s *= a.scale[k];
-    v.x = (typename RealOf<C>::T)(v.x * s);
-    v.y = (typename RealOf<C>::T)(v.y * s);
-    store_as<C>(out, (o * a.n + k) * a.S + i, a.out_kind, v, a.accumulate);
-  }
-}
-
 }  // namespace
-
-hipError_t launch_chirp(const ChirpArgs& a, bool fp32, const void* in, void* out, hipStream_t s) {
-  const int64_t K = a.post ? a.n : a.M;
-  const int64_t nib = (a.S + 255) / 256;
-  if (a.O <= 0 || K <= 0 || a.S <= 0) return hipSuccess;
-  if (a.O > 65535 || K * nib > 0x7fffffffLL) return hipErrorInvalidValue;
-  const dim3 grid((unsigned)(K * nib), (unsigned)a.O);
-  if (fp32)
-    hipLaunchKernelGGL(chirp_kernel<float2>, grid, dim3(256), 0, s, a, in, out, nib);
-  else
-    hipLaunchKernelGGL(chirp_kernel<double2>, grid, dim3(256), 0, s, a, in, out, nib);
-  return hipGetLastError();
-}
 
 int fft_tile_width(int L, bool fp32) { return fp32 ? tile_w<float2>(L) : tile_w<double2>(L); }
 
-hipError_t launch_fft_pass(const FftPass& f, bool fp32, const void* in, void* out, hipStream_t s) {
+static PassDev make_pass_dev(const FftPass& f) {
   PassDev p;
   p.I = f.I;
   p.od = f.od;
@@ -339,9 +389,28 @@ hipError_t launch_fft_pass(const FftPass& f, bool fp32, const void* in, void* ou
   p.sign = f.sign;
   p.cmode = f.cmode;
   p.skip = f.skip;
+  p.cin = f.cin;
+  p.cout = f.cout;
+  p.chirp_n = f.chirp_n;
+  p.chirp_na = f.chirp_na;
+  p.chirp_S = f.chirp_S > 0 ? f.chirp_S : 1;
+  p.tw4_mode = f.tw4_mode;
+  p.conj_out = f.conj_out;
   p.ntile = 0;
-  if (f.tw4 && f.tw4_S <= 0) return hipErrorInvalidValue;
+  return p;
+}
+
+hipError_t launch_fft_pass(const FftPass& f, bool fp32, const void* in, void* out, hipStream_t s) {
+  if (f.tw4 && f.tw4_mode == 0 && f.tw4_S <= 0) return hipErrorInvalidValue;
+  const PassDev p = make_pass_dev(f);
   return fp32 ? launch_typed<float2>(f.L, p, f.O, in, out, s) : launch_typed<double2>(f.L, p, f.O, in, out, s);
+}
+
+hipError_t launch_conv_pass(const FftPass& f, bool fp32, const void* in, void* out, hipStream_t s) {
+  if (!f.cmode) return hipErrorInvalidValue;
+  const PassDev p = make_pass_dev(f);
+  return fp32 ? launch_conv_typed<float2>(f.L, p, f.O, in, out, s)
+              : launch_conv_typed<double2>(f.L, p, f.O, in, out, s);
 }
 
 }  // namespace helm

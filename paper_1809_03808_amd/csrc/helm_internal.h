@@ -93,30 +93,30 @@ struct FftPass {
   const double* scale = nullptr;
   const void* cmode = nullptr;  // optional complex per-mode multiplier (compute precision)
   const int* skip = nullptr;    // device flag: when non-zero the pass does nothing
+  // Chirp-z folding (compute precision tables): with the row map
+  // x = col / chirp_S + chirp_na * row, the first stage loads in * cin[x] for
+  // x < chirp_n and zero beyond, and the last stage stores y * cout[x] for
+  // x < chirp_n only.
+  const void* cin = nullptr;
+  const void* cout = nullptr;
+  int64_t chirp_n = 0, chirp_na = 1, chirp_S = 1;
+  // Twiddle index of the last stage: 0 -> tw4[k a] with a = col / tw4_S
+  // (four-step first pass), 1 -> tw4[k c] with c the group index within od.
+  int tw4_mode = 0;
+  int conj_out = 0;  // store the complex conjugate (before the twiddle)
 };
 
 // Inner columns per tile of a length-L pass (fixed per length and precision).
 int fft_tile_width(int L, bool fp32);
+// Middle of a chirp-z convolution: for every group (o, c) of the pass
+// geometry, a length-L forward DFT over the rows, multiplication by
+// cmode[c + od d] (the transformed chirp kernel), and the unscaled inverse
+// DFT back over the rows, with the epilogue of the pass (tw4_mode 1 twiddle).
+hipError_t launch_conv_pass(const FftPass& p, bool fp32, const void* in, void* out, hipStream_t s);
 // Launch one pass.  `fp32` selects float arithmetic (tables in float).
 hipError_t launch_fft_pass(const FftPass& p, bool fp32, const void* in, void* out,
                            hipStream_t s);
 
-// Chirp step of Bluestein's algorithm for a length-n DFT along the axis of
-// [O][n][S] data, with a power-of-two convolution length M >= 2n - 1:
-//   pre  (post = 0): t[o][j][i] = x[o][j][i] w[j] for j < n, 0 for n <= j < M
-//   post (post = 1): y[o][k][i] (+)= w[k] t[o][k][i] scale[k] scale_c, k < n
-// w[j] = e^{sign pi i j^2 / n} (table, compute precision).
-struct ChirpArgs {
-  int post = 0;
-  int64_t O = 0, n = 0, M = 0, S = 0;
-  int in_kind = ST_C128, out_kind = ST_C128;
-  const void* w = nullptr;
-  const double* scale = nullptr;
-  double scale_c = 1.0;
-  int accumulate = 0;
-  const int* skip = nullptr;
-};
-hipError_t launch_chirp(const ChirpArgs& a, bool fp32, const void* in, void* out, hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // Batched tridiagonal line solves (lines.hip)
@@ -153,6 +153,7 @@ struct LineArgs {
   const double2* rho1 = nullptr;
   double2* part = nullptr;
   const double2* piv = nullptr;  // [nO*nI][P] reciprocal pivot entering each lane chunk
+  const double2* sTab = nullptr; // [nO*nI] sigma of every line (replaces sO + sI + sC when set)
   int tile = 0;    // lines per workgroup tile
   int ntiles = 0;  // tiles along the reduced (or flattened) index
   const int* skip = nullptr;     // device flag: the launch does nothing while *skip != 0

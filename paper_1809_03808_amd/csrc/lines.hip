@@ -171,6 +171,7 @@ struct LineDev {
   const void* in;
   const double2 *alpha0, *alpha1, *PO, *beta0, *beta1, *PI, *rho0, *rho1;
   const double2* piv;   // [nO*nI][P]: reciprocal pivot entering the chunk of each lane
+  const double2* sTab;  // [nO*nI] sigma per line, or null
   void* out;
   double2* part;
   const int* skip;
@@ -181,9 +182,14 @@ struct RowCoef {
 };
 
 __device__ inline RowCoef row_coef(const LineDev& a, int64_t l, int64_t m) {
-  double2 sig = a.sC;
-  if (a.sO) sig = cadd(sig, a.sO[l]);
-  if (a.sI) sig = cadd(sig, a.sI[m]);
+  double2 sig;
+  if (a.sTab) {
+    sig = a.sTab[l * a.nI + m];
+  } else {
+    sig = a.sC;
+    if (a.sO) sig = cadd(sig, a.sO[l]);
+    if (a.sI) sig = cadd(sig, a.sI[m]);
+  }
   RowCoef r;
   r.off = make_double2(sig.x * a.m_off + a.k_off, sig.y * a.m_off);  // sigma h/6 - 1/h
   r.off2 = cmul(r.off, r.off);
@@ -293,6 +299,29 @@ __global__ __launch_bounds__(NT) void lines_kernel(LineDev a) {
     for (int j = 0; j < kCMax; ++j) acc0[j] = acc1[j] = make_double2(0, 0);
   }
 
+  // Reducing launches whose lines span whole waves (P >= 64) prefetch the
+  // next line's input rows into registers while the current line is solved,
+  // so the load latency overlaps the sweeps.
+  constexpr bool PREF = P >= 64 && RED;
+  T pre[PREF ? kCMax : 1];
+  auto fetch = [&](int itn) {
+    uint32_t sb, sl, sm;
+    const bool sv = decode_line(a, g, t, LPB, itn, wslot0, sb, sl, sm);
+    const int64_t soff = ((int64_t)(sb * a.nO + sl) * a.nI + sm) * nL;
+#pragma unroll
+    for (int jj = 0; jj < kCMax; ++jj) {
+      const int r = jj * 64 + lane, x = wx0 + r;
+      T v;
+      v.x = 0;
+      v.y = 0;
+      if (r < seg && x < nL && sv) v = reinterpret_cast<const T*>(a.in)[soff + x];
+      pre[jj] = v;
+    }
+  };
+  if constexpr (PREF) {
+    if (a.in && a.iters > 0) fetch(0);
+  }
+
   for (int it = 0; it < a.iters; ++it) {
     // ---- right-hand side, staged through LDS -------------------------------
 #pragma unroll 4
@@ -307,7 +336,14 @@ __global__ __launch_bounds__(NT) void lines_kernel(LineDev a) {
       const double2* pi = a.PI ? a.PI + (int64_t)((sb * a.nO + sl) * 2) * nL : nullptr;
       // one source at a time (each lane revisits only its own staging slots),
       // so that at most kCMax loads are in flight per lane
-      if (a.in) {
+      if (a.in && PREF) {
+#pragma unroll
+        for (int jj = 0; jj < kCMax; ++jj) {
+          const int r = jj * 64 + lane;
+          if (r < seg) S[stage_pos(si * seg + r)] = to_d2(pre[jj]);
+        }
+        if (it + 1 < a.iters) fetch(it + 1);
+      } else if (a.in) {
         double2 d[kCMax];
 #pragma unroll
         for (int jj = 0; jj < kCMax; ++jj) {
@@ -600,6 +636,7 @@ LineDev make_dev(const LineArgs& a, int P, int c) {
   d.beta0 = a.beta0; d.beta1 = a.beta1; d.PI = a.PI;
   d.rho0 = a.rho0; d.rho1 = a.rho1;
   d.piv = a.piv;
+  d.sTab = a.sTab;
   d.out = a.out; d.part = a.part;
   d.skip = a.skip;
   d.tile = d.ntiles = d.iters = 0;

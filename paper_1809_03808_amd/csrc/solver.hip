@@ -66,7 +66,12 @@ struct PAxis {
   double h = 0;
   int lo = 0, hi = 0;
   std::vector<cd> lamA, va0, va1;
+  // spectra to extended precision (host), for the shifted values below
+  std::vector<long double> lamBx;
+  std::vector<std::complex<long double>> lamAx;
   DevMem tab;  // all per-mode tables below, one allocation
+  // sigB / sigA: lambda - w^2 of the periodic / absorbing spectra, formed in
+  // extended precision and rounded once
   double2 *sigB = nullptr, *sigA = nullptr, *genB0 = nullptr, *genB1 = nullptr, *redB0 = nullptr,
           *redB1 = nullptr, *va0d = nullptr, *va1d = nullptr;
   double* invmu = nullptr;
@@ -108,12 +113,15 @@ struct helm_plan {
   // workspace
   int cap_rhs = 0;
   int cap_prec = -1;
-  helm::DevMem W0, W1, W2, R, part, VB, PIb, P0, P1, P2, P3, scratch, norms, BT1, BT2;
+  helm::DevMem W0, W1, W2, R, part, VB, PIb, P0, P1, P2, P3, scratch, norms, BT1;
   // LU factor tables (reciprocal Thomas pivots) per line-matrix family
   // (outer branch, inner branch): [0] = (B, B), [1] = (B, A), [2] = (A, B),
   // [3] = (A, A); 2D uses [0], [1].
   helm::DevMem factors;
   const double2* seed[4] = {nullptr, nullptr, nullptr, nullptr};
+  // per family, sigma of every line matrix [nO][nI] (same family order)
+  helm::DevMem sigtab;
+  const double2* sig[4] = {nullptr, nullptr, nullptr, nullptr};
   // device-side refinement control (IrCtl) for captured solves
   helm::DevMem ctl;
   int dense = 0;  // 1: periodised axes use the dense eigenvector transforms
@@ -404,50 +412,166 @@ int run_pow2(helm_plan* p, int L, int na, int nb, int sign, bool fp32, const voi
 // DFT along a periodised axis of data [O][n][S] (S contiguous).
 // Forward: sign -1 and per-mode scale 1/mu (if scale), inverse: sign +1, 1/n.
 // Lengths that are not powers of two use Bluestein's chirp-z algorithm:
-// jk = (j^2 + k^2 - (k - j)^2)/2 turns the DFT into a convolution, evaluated
-// with power-of-two transforms of length M >= 2n - 1 in the plan's BT1/BT2.
+// jk = (j^2 + k^2 - (k - j)^2)/2 turns the DFT into a convolution with the
+// chirp kernel, evaluated with power-of-two transforms of length M >= 2n - 1.
+// The chirp multiplications are folded into the first load and the last
+// store, and the convolution's middle (forward pass, kernel product, inverse
+// pass) is one kernel, so a transform costs n + M + 2M + M + n element moves
+// (M <= 512: n + M + M + n) in the plan's temporary BT1.
 int run_fft(helm_plan* p, const PAxis& a, int sign, bool fp32, const void* in, int in_kind, void* out,
             int out_kind, int64_t O, int64_t S, const double* scale, double scale_c, int accumulate,
             void* tmp, int tmp_kind, hipStream_t st, const int* skip = nullptr) {
   if (!a.blue)
     return run_pow2(p, a.n, a.na, a.nbp, sign, fp32, in, in_kind, out, out_kind, O, S, scale, scale_c,
                     nullptr, accumulate, tmp, tmp_kind, skip, st);
-  const int si = sign < 0 ? 0 : 1;
-  const int T = fp32 ? ST_C64 : ST_C128;
-  void* t1 = p->BT1.p;
-  void* t2 = p->BT2.p;
-  ChirpArgs c;
-  c.O = O;
-  c.n = a.n;
-  c.M = a.M;
-  c.S = S;
-  c.w = fp32 ? a.chirp_f[si] : a.chirp_d[si];
-  c.skip = skip ? skip : p->skip_cur;
-  c.post = 0;
-  c.in_kind = in_kind;
-  c.out_kind = T;
-  const double byc = (double)O * S * ((double)a.n * esz_of(in_kind) + (double)a.M * esz_of(T));
-  HCHK(timed(p, fp32 ? K_FFT32 : K_FFT64, byc, st, [&] { return launch_chirp(c, fp32, in, t1, st); }));
-  int rc = run_pow2(p, a.M, a.Mna, a.Mnbp, -1, fp32, t1, T, t1, T, O, S, nullptr, 1.0,
-                    fp32 ? a.bhat_f[si] : a.bhat_d[si], 0, t2, T, skip, st);
-  if (rc) return rc;
-  rc = run_pow2(p, a.M, a.Mna, a.Mnbp, +1, fp32, t1, T, t1, T, O, S, nullptr, 1.0, nullptr, 0, t2, T, skip, st);
-  if (rc) return rc;
-  c.post = 1;
-  c.in_kind = T;
-  c.out_kind = out_kind;
-  c.scale = scale;
-  c.scale_c = scale_c / a.M;
-  c.accumulate = accumulate;
-  const double byp = (double)O * S * ((double)a.M * esz_of(T) + (double)a.n * esz_of(out_kind) * (accumulate ? 2 : 1));
-  HCHK(timed(p, fp32 ? K_FFT32 : K_FFT64, byp, st, [&] { return launch_chirp(c, fp32, t1, out, st); }));
   (void)tmp;
   (void)tmp_kind;
+  const int si = sign < 0 ? 0 : 1;
+  const int T = fp32 ? ST_C64 : ST_C128;
+  const int64_t n = a.n, M = a.M;
+  void* t1 = p->BT1.p;
+  const void* chirp = fp32 ? a.chirp_f[si] : a.chirp_d[si];
+  const void* bhat = fp32 ? a.bhat_f[si] : a.bhat_d[si];
+  const int* sk = skip ? skip : p->skip_cur;
+  const int K = fp32 ? K_FFT32 : K_FFT64;
+  if (a.Mna <= 1) {
+    Roots* rf = get_roots(p, (int)M, -1);
+    Roots* ri = get_roots(p, (int)M, +1);
+    if (!rf || !ri) return HELM_ENOMEM;
+    FftPass f;
+    f.L = (int)M;
+    radix_plan((int)M, f);
+    f.I = S;
+    f.O = O;
+    f.od = 1;
+    f.in_so = n * S;
+    f.in_sj = S;
+    f.out_so1 = M * S;
+    f.out_sk = S;
+    f.in_kind = in_kind;
+    f.out_kind = T;
+    f.sign = -1;
+    f.tw = fp32 ? rf->f.p : rf->d.p;
+    f.cin = chirp;
+    f.chirp_n = n;
+    f.chirp_na = 1;
+    f.chirp_S = S;
+    f.cmode = bhat;
+    f.skip = sk;
+    const double by1 = (double)O * S * ((double)n * esz_of(in_kind) + (double)M * esz_of(T));
+    HCHK(timed(p, K, by1, st, [&] { return launch_fft_pass(f, fp32, in, t1, st); }));
+    FftPass g = f;
+    g.in_so = M * S;
+    g.out_so1 = n * S;
+    g.in_kind = T;
+    g.out_kind = out_kind;
+    g.sign = +1;
+    g.tw = fp32 ? ri->f.p : ri->d.p;
+    g.cin = nullptr;
+    g.cmode = nullptr;
+    g.cout = chirp;
+    g.scale = scale;
+    g.scale_c = scale_c / (double)M;
+    g.accumulate = accumulate;
+    const double by2 = (double)O * S * ((double)M * esz_of(T) + (double)n * esz_of(out_kind) * (accumulate ? 2 : 1));
+    HCHK(timed(p, K, by2, st, [&] { return launch_fft_pass(g, fp32, t1, out, st); }));
+    return HELM_OK;
+  }
+  // four-step convolution, M = na * nb: x = a + na b, k = c + nb d
+  const int na = a.Mna, nb = a.Mnbp;
+  Roots* rbf = get_roots(p, nb, -1);
+  Roots* rbi = get_roots(p, nb, +1);
+  Roots* raf = get_roots(p, na, -1);
+  Roots* rMf = get_roots(p, (int)M, -1);
+  Roots* rMi = get_roots(p, (int)M, +1);
+  if (!rbf || !rbi || !raf || !rMf || !rMi) return HELM_ENOMEM;
+  // 1: length-nb DFTs over b of the chirped input rows (zero past n), twiddle
+  //    e^{-2 pi i a c / M}, into t1[o][c][a][s]
+  FftPass f1;
+  f1.L = nb;
+  radix_plan(nb, f1);
+  f1.I = (int64_t)na * S;
+  f1.O = O;
+  f1.od = 1;
+  f1.in_so = n * S;
+  f1.in_sj = (int64_t)na * S;
+  f1.out_so1 = M * S;
+  f1.out_sk = (int64_t)na * S;
+  f1.tw4_S = S;
+  f1.tw4_n = (int)M;
+  f1.in_kind = in_kind;
+  f1.out_kind = T;
+  f1.sign = -1;
+  f1.tw = fp32 ? rbf->f.p : rbf->d.p;
+  f1.tw4 = fp32 ? rMf->f.p : rMf->d.p;
+  f1.cin = chirp;
+  f1.chirp_n = n;
+  f1.chirp_na = na;
+  f1.chirp_S = S;
+  f1.skip = sk;
+  const double by1 = (double)O * S * ((double)n * esz_of(in_kind) + (double)M * esz_of(T));
+  HCHK(timed(p, K, by1, st, [&] { return launch_fft_pass(f1, fp32, in, t1, st); }));
+  // 2: per group c, length-na DFT over a, product with the transformed
+  //    kernel at k = c + nb d, unscaled inverse over d, twiddle
+  //    e^{+2 pi i c a / M}; in place
+  FftPass f2;
+  f2.L = na;
+  radix_plan(na, f2);
+  f2.I = S;
+  f2.O = O * nb;
+  f2.od = nb;
+  f2.in_so = (int64_t)na * S;
+  f2.in_sj = S;
+  f2.out_so1 = M * S;
+  f2.out_so2 = (int64_t)na * S;
+  f2.out_sk = S;
+  f2.in_kind = T;
+  f2.out_kind = T;
+  f2.sign = -1;
+  f2.tw = fp32 ? raf->f.p : raf->d.p;
+  f2.cmode = bhat;
+  f2.tw4 = fp32 ? rMi->f.p : rMi->d.p;
+  f2.tw4_n = (int)M;
+  f2.tw4_mode = 1;
+  f2.conj_out = 1;
+  f2.skip = sk;
+  const double by2 = (double)O * S * (double)M * 2.0 * esz_of(T);
+  HCHK(timed(p, K, by2, st, [&] { return launch_conv_pass(f2, fp32, t1, t1, st); }));
+  // 3: per a, length-nb inverse DFT over c, rows x = a + na b < n stored with
+  //    the chirp, the per-mode scale and 1/M
+  FftPass f3;
+  f3.L = nb;
+  radix_plan(nb, f3);
+  f3.I = (int64_t)na * S;
+  f3.O = O;
+  f3.od = 1;
+  f3.in_so = M * S;
+  f3.in_sj = (int64_t)na * S;
+  f3.out_so1 = n * S;
+  f3.out_sk = (int64_t)na * S;
+  f3.in_kind = T;
+  f3.out_kind = out_kind;
+  f3.sign = +1;
+  f3.tw = fp32 ? rbi->f.p : rbi->d.p;
+  f3.cout = chirp;
+  f3.chirp_n = n;
+  f3.chirp_na = na;
+  f3.chirp_S = S;
+  f3.scale = scale;
+  f3.scale_c = scale_c / (double)M;
+  f3.accumulate = accumulate;
+  f3.skip = sk;
+  const double by3 = (double)O * S * ((double)M * esz_of(T) + (double)n * esz_of(out_kind) * (accumulate ? 2 : 1));
+  HCHK(timed(p, K, by3, st, [&] { return launch_fft_pass(f3, fp32, t1, out, st); }));
   return HELM_OK;
 }
 
 // Lines per tile: at least 8 lines feed each partial sum (partials stay
-// below 1/4 of an N-sized array) and enough tiles to fill the chip.
+// below 1/4 of an N-sized array).  A reducing launch writes one partial of
+// 2 nL values per block, so it uses about as many blocks as stay resident
+// at once (one 512-thread or two 256-thread blocks per compute unit at the
+// register use of the reducing kernels) and no more; other launches take up
+// to 2048 blocks.
 void tiles_for(int red, int nb, int nO, int nI, int nL, int* tile, int* ntiles) {
   int P, c, NT;
   lines_geometry(nL, &P, &c, &NT);
@@ -456,7 +580,7 @@ void tiles_for(int red, int nb, int nO, int nI, int nL, int* tile, int* ntiles) 
   const int64_t groups = red == 1 ? (int64_t)nb * nO : (red == 2 ? (int64_t)nb * nI : 1);
   int64_t t = red ? 8 : LPB;
   const int64_t lines = extent * groups;
-  const int64_t target = 2048;
+  const int64_t target = red ? (NT >= 512 ? 256 : 512) : 2048;
   if (lines / t > target) t = (lines + target - 1) / target;
   if (red && t > extent) t = extent;
   t = (t + LPB - 1) / LPB * LPB;
@@ -493,6 +617,8 @@ struct InnerIO {
   const double2* rhoL1 = nullptr;
   const double2* seedB = nullptr;  // line matrices with the periodic inner branch (S1, S3)
   const double2* seedA = nullptr;  // line matrices with the absorbing inner branch (S2)
+  const double2* sigTB = nullptr;  // their sigma tables
+  const double2* sigTA = nullptr;
 };
 
 int inner_solve(helm_plan* p, const Level& lv, const InnerIO& io, hipStream_t st) {
@@ -510,6 +636,7 @@ int inner_solve(helm_plan* p, const Level& lv, const InnerIO& io, hipStream_t st
   base.kLo = p->kLo;
   base.kHi = p->kHi;
   base.piv = io.seedB;
+  base.sTab = io.sigTB;
   double2* part = p->part.as<double2>();
   const double elems = (double)lv.nb * lv.nO * lv.nI * lv.nL;
   int tile, nt;
@@ -541,8 +668,8 @@ int inner_solve(helm_plan* p, const Level& lv, const InnerIO& io, hipStream_t st
   m.vb_in = nullptr;
   m.vb_out = p->VB.as<double2>();
   m.out = p->PIb.as<double2>();
-  m.sO = io.sO;
-  m.sC = sC;
+  m.sO = io.sO;                                  // lambda_outer - w^2 (3D) or none
+  m.sC = io.sO ? make_double2(0.0, 0.0) : sC;   // p_l = -(sO[l] + sC)
   m.d = I.bd;
   m.hL = p->hL;
   m.kLo = p->kLo;
@@ -554,6 +681,7 @@ int inner_solve(helm_plan* p, const Level& lv, const InnerIO& io, hipStream_t st
   LineArgs s2 = base;
   s2.sI = I.sigA;
   s2.piv = io.seedA;
+  s2.sTab = io.sigTA;
   s2.PI = p->PIb.as<double2>();
   s2.beta0 = I.va0d;
   s2.beta1 = I.va1d;
@@ -677,7 +805,7 @@ int solve_dense(helm_plan* p, const void* x, int x_kind, double2* u, int accumul
     if (rc) return rc;
     la.nO = 1;
     la.nI = n1;
-    la.sI = A1.sigA;
+    la.sTab = p->sig[1];
     la.piv = p->seed[1];
     la.in = W0;
     la.out = W0;
@@ -694,8 +822,7 @@ int solve_dense(helm_plan* p, const void* x, int x_kind, double2* u, int accumul
   if (rc) return rc;
   la.nO = n1;
   la.nI = n2;
-  la.sO = A1.sigA;
-  la.sI = A2.sigA;
+  la.sTab = p->sig[3];
   la.piv = p->seed[3];
   la.in = W1;
   la.out = W1;
@@ -727,6 +854,8 @@ int solve_once(helm_plan* p, const void* x, int x_kind, double2* u, int accumula
     io.out_kind = T;
     io.seedB = p->seed[0];
     io.seedA = p->seed[1];
+    io.sigTB = p->sig[0];
+    io.sigTA = p->sig[1];
     rc = inner_solve(p, lv, io, st);
     if (rc) return rc;
     return run_fft(p, A1, +1, fp32, W0, T, u, ST_C128, nb, n2, nullptr, 1.0 / n1, accumulate, W1, T, st);
@@ -754,6 +883,8 @@ int solve_once(helm_plan* p, const void* x, int x_kind, double2* u, int accumula
     io.sO = A1.sigB;
     io.seedB = p->seed[0];
     io.seedA = p->seed[1];
+    io.sigTB = p->sig[0];
+    io.sigTA = p->sig[1];
     io.in = W0;
     io.in_kind = T;
     io.rhoL0 = A1.redB0;
@@ -792,6 +923,8 @@ int solve_once(helm_plan* p, const void* x, int x_kind, double2* u, int accumula
     io.sO = A1.sigA;
     io.seedB = p->seed[2];
     io.seedA = p->seed[3];
+    io.sigTB = p->sig[2];
+    io.sigTA = p->sig[3];
     io.PO = Rh;
     io.alpha0 = A1.va0d;
     io.alpha1 = A1.va1d;
@@ -819,6 +952,8 @@ int solve_once(helm_plan* p, const void* x, int x_kind, double2* u, int accumula
     io.sO = A1.sigB;
     io.seedB = p->seed[0];
     io.seedA = p->seed[1];
+    io.sigTB = p->sig[0];
+    io.sigTA = p->sig[1];
     io.in = W0;
     io.in_kind = T;
     io.PO = Rh;
@@ -880,10 +1015,7 @@ int ensure_workspace(helm_plan* p, int nb, bool fp32, bool need_r) {
       if (p->ax[1].blue)
         tmax = std::max(tmax, (size_t)nb * std::max(p->ax[0].n, 2) * p->ax[1].M * p->nL);
     }
-    if (tmax) {
-      HCHK(p->BT1.ensure(tmax * sizeof(double2)));
-      HCHK(p->BT2.ensure(tmax * sizeof(double2)));
-    }
+    if (tmax) HCHK(p->BT1.ensure(tmax * sizeof(double2)));
   }
   HCHK(p->scratch.ensure((size_t)residual_scratch_len(p->dim, p->grid, nb) * sizeof(double)));
   HCHK(p->norms.ensure((size_t)nb * 2 * sizeof(double)));
@@ -971,16 +1103,23 @@ void fill_axis_tables_host(PAxis& a, double omega, std::vector<double2>& buf, st
   const double h = a.h;
   buf.assign((size_t)n * 8, make_double2(0, 0));
   invmu.assign(n, 0.0);
+  a.lamBx.assign(n, 0.0L);
   for (int l = 0; l < n; ++l) {
     const double th = 2.0 * M_PI * l / n;
     const double sh = std::sin(0.5 * th);
     const double omc = 2.0 * sh * sh;  // 1 - cos(theta) without cancellation
     const double cth = 1.0 - omc;
     const double mu = h / 6.0 * (4.0 + 2.0 * cth);
-    const double lamB = 6.0 * omc / (h * h * (2.0 + cth));
+    const long double w2x = (long double)omega * (long double)omega;
+    const long double thx = 2.0L * (long double)M_PI * l / n;
+    const long double shx = std::sin(0.5L * thx);
+    const long double omcx = 2.0L * shx * shx;
+    const long double lamBx = 6.0L * omcx / ((long double)h * (long double)h * (3.0L - omcx));
+    a.lamBx[l] = lamBx;
     const double c = std::cos(th), s = std::sin(th);
-    buf[0 * n + l] = make_double2(lamB, 0.0);                              // sigB
-    buf[1 * n + l] = hd2(a.lamA[l]);                                       // sigA
+    buf[0 * n + l] = make_double2((double)(lamBx - w2x), 0.0);             // sigB = lambda_B - w^2
+    buf[1 * n + l] = make_double2((double)(a.lamAx[l].real() - w2x),       // sigA = lambda_A - w^2
+                                  (double)a.lamAx[l].imag());
     buf[2 * n + l] = make_double2(1.0 / mu, 0.0);                          // genB0
     buf[3 * n + l] = make_double2(c / mu, s / mu);                         // genB1 = e^{+i th}/mu
     buf[4 * n + l] = make_double2(1.0 / n, 0.0);                           // redB0
@@ -1304,9 +1443,13 @@ int helm_setup(int dim, const int64_t* grid, const double* h, double omega, uint
       const int bst = setup_bluestein(a);
       if (bst != HELM_OK) return bst;
     }
-    std::vector<cd> vfull;
-    const int st = eig1d(a.n, a.h, omega, a.lo, a.hi, a.lamA, a.va0, a.va1, dense_ok ? &vfull : nullptr);
+    std::vector<cd> vfull, lamlo;
+    const int st = eig1d(a.n, a.h, omega, a.lo, a.hi, a.lamA, a.va0, a.va1, dense_ok ? &vfull : nullptr, &lamlo);
     if (st != HELM_OK) return st;
+    a.lamAx.resize(a.n);
+    for (int l = 0; l < a.n; ++l)
+      a.lamAx[l] = std::complex<long double>((long double)a.lamA[l].real() + lamlo[l].real(),
+                                             (long double)a.lamA[l].imag() + lamlo[l].imag());
     if (dense_ok) {
       const int ast = upload_eigvecs(a, vfull);
       if (ast != HELM_OK) return ast;
@@ -1330,30 +1473,49 @@ int helm_setup(int dim, const int64_t* grid, const double* h, double omega, uint
     a.va1d = t + 7 * a.n;
     a.invmu = reinterpret_cast<double*>((char*)a.tab.p + nb2);
   }
-  // LU factors (reciprocal Thomas pivots) of every line-matrix family: sigma
-  // depends on the outer and inner branches only (Section 4.1.2 computes the
-  // LU decompositions of H_B and H_A at initialisation).
+  // Line-matrix families (outer branch, inner branch): the shift
+  // sigma = lambda_outer + lambda_inner - w^2 of every line, formed in extended
+  // precision and rounded once (near-resonant modes would otherwise lose
+  // digits to cancellation against w^2), and the LU factors (reciprocal Thomas
+  // pivots; Section 4.1.2 computes the LU decompositions of H_B and H_A at
+  // initialisation).
   {
     const int nO = dim == 2 ? 1 : p->ax[0].n;
     const int nI = p->ax[dim - 2].n;
     const int fam = dim == 2 ? 2 : 4;
+    const PAxis& inner = p->ax[dim - 2];
+    const size_t pairs = (size_t)nO * nI;
+    std::vector<double2> hs(pairs * fam);
+    const long double w2x = (long double)omega * (long double)omega;
+    for (int k = 0; k < fam; ++k) {
+      for (int l = 0; l < nO; ++l) {
+        std::complex<long double> so(0.0L, 0.0L);
+        if (dim == 3) so = (k & 2) ? p->ax[0].lamAx[l] : std::complex<long double>(p->ax[0].lamBx[l], 0.0L);
+        for (int m = 0; m < nI; ++m) {
+          const std::complex<long double> si =
+              (k & 1) ? inner.lamAx[m] : std::complex<long double>(inner.lamBx[m], 0.0L);
+          const std::complex<long double> sg = so + si - w2x;
+          hs[pairs * k + (size_t)l * nI + m] = make_double2((double)sg.real(), (double)sg.imag());
+        }
+      }
+    }
+    if (p->sigtab.ensure(hs.size() * sizeof(double2)) != hipSuccess) return HELM_ENOMEM;
+    if (upload(p->sigtab.p, hs.data(), hs.size() * sizeof(double2)) != hipSuccess) return HELM_EDEVICE;
     int P, c, NT;
     lines_geometry(p->nL, &P, &c, &NT);
-    const size_t per = (size_t)nO * nI * P;
+    const size_t per = pairs * P;
     if (p->factors.ensure(per * fam * sizeof(double2)) != hipSuccess) return HELM_ENOMEM;
     for (int k = 0; k < fam; ++k) {
+      p->sig[k] = p->sigtab.as<double2>() + pairs * k;
       LineArgs la;
       la.nb = 1;
       la.nO = nO;
       la.nI = nI;
       la.nL = p->nL;
-      la.sC = make_double2(-omega * omega, 0.0);
+      la.sTab = p->sig[k];
       la.hL = p->hL;
       la.kLo = p->kLo;
       la.kHi = p->kHi;
-      const PAxis& inner = p->ax[dim - 2];
-      la.sI = (k & 1) ? inner.sigA : inner.sigB;
-      la.sO = dim == 2 ? nullptr : ((k & 2) ? p->ax[0].sigA : p->ax[0].sigB);
       double2* dst = p->factors.as<double2>() + per * k;
       if (launch_line_factors(la, dst, nullptr) != hipSuccess) return HELM_EDEVICE;
       p->seed[k] = dst;

@@ -12,6 +12,8 @@
 //                              + M1(o1) M2(o2) (K3 u_{o1,o2})_x,
 // with S1 = K1 - w^2 M1.  Norm partials are reduced per block in LDS and
 // summed per right-hand side in a fixed order, so the result is deterministic.
+#include <algorithm>
+
 #include "helm_internal.h"
 #include "ops1d.h"
 
@@ -42,13 +44,23 @@ __device__ inline void row_ops(const double2* v, int n, double h, double2 kLo, d
   }
 }
 
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own
+// L2).  Renumber them so that every XCD works on one contiguous range of
+// lines: the neighbouring lines a stencil row reads are then mostly in the
+// same L2.  A bijection on [0, n) for any n.
+__device__ inline int64_t xcd_contiguous(int64_t b, int64_t n) {
+  const int64_t q = n / 8, r = n % 8, x = b % 8, k = b / 8;
+  return x < r ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
+}
+
 template <typename TR>
 __global__ __launch_bounds__(kResThreads) void residual_kernel(ResidArgs a, int64_t per_rhs,
                                                                int64_t quads_per_rhs, int64_t blocks_per_rhs) {
   __shared__ double red[2][kResThreads];
   if (a.skip && *a.skip) return;
-  const int64_t b = blockIdx.x / blocks_per_rhs;
-  const int64_t qi = (blockIdx.x % blocks_per_rhs) * kResThreads + threadIdx.x;
+  const int64_t bid = xcd_contiguous(blockIdx.x, gridDim.x);
+  const int64_t b = bid / blocks_per_rhs;
+  const int64_t qi = (bid % blocks_per_rhs) * kResThreads + threadIdx.x;
   double sr = 0.0, sf = 0.0;
   if (qi < quads_per_rhs) {
     const int dim = a.dim;
@@ -134,8 +146,243 @@ __global__ __launch_bounds__(kResThreads) void residual_kernel(ResidArgs a, int6
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    a.scratch[2 * blockIdx.x] = red[0][0];
-    a.scratch[2 * blockIdx.x + 1] = red[1][0];
+    a.scratch[2 * bid] = red[0][0];
+    a.scratch[2 * bid + 1] = red[1][0];
+  }
+}
+
+// 2D: one thread per column x, a block streams down a strip of kStrip rows
+// of 256 columns.  Each row of u is loaded once (consecutive lanes on
+// consecutive columns), its x_2 neighbours come from the adjacent lanes
+// (the two wave-edge lanes load theirs), and the row operators M_2 u_j and
+// K_2 u_j of rows i-1, i, i+1 stay in registers while the strip advances,
+// so u and f are read from memory once (plus two halo rows per strip).  The
+// rows one and two ahead are already in flight while row i is combined.
+constexpr int kStrip = 32;
+
+struct RowRaw {
+  double2 c, e;  // u[j][x], and u[j][x -/+ 1] for the first / last lane of the wave
+};
+
+template <typename TR>
+__global__ __launch_bounds__(kResThreads) void residual2d_kernel(ResidArgs a, int64_t xtiles,
+                                                                 int64_t blocks_per_rhs) {
+  __shared__ double red[2][kResThreads];
+  if (a.skip && *a.skip) return;
+  const int64_t bid = xcd_contiguous(blockIdx.x, gridDim.x);
+  const int64_t b = bid / blocks_per_rhs;
+  const int64_t rem = bid - b * blocks_per_rhs;
+  const int64_t si = rem / xtiles, xi = rem - si * xtiles;
+  const AxisOp& A1 = a.ax[0];
+  const AxisOp& A2 = a.ax[1];
+  const int n1 = A1.n, n2 = A2.n;
+  const int x = (int)xi * kResThreads + (int)threadIdx.x;
+  const bool xok = x < n2;
+  const int lane = threadIdx.x & 63;
+  const int r0 = (int)si * kStrip, r1 = min(n1, r0 + kStrip);
+  const int64_t off = b * (int64_t)n1 * n2;
+  const double2* U = a.u + off;
+  const int xe = lane == 0 ? x - 1 : x + 1;  // edge neighbour loaded by the wave-edge lanes
+  const bool edge = (lane == 0 || lane == 63) && xe >= 0 && xe < n2;
+  const double mL = m1d(n2, A2.h, x, -1), mC = m1d(n2, A2.h, x, 0), mR = m1d(n2, A2.h, x, 1);
+  const double2 kL = k1d(n2, A2.h, A2.kLo, A2.kHi, x, -1), kC = k1d(n2, A2.h, A2.kLo, A2.kHi, x, 0),
+                kR = k1d(n2, A2.h, A2.kLo, A2.kHi, x, 1);
+  auto load = [&](int j) {
+    RowRaw w;
+    w.c = make_double2(0, 0);
+    w.e = make_double2(0, 0);
+    if (j >= 0 && j < n1) {
+      const double2* row = U + (int64_t)j * n2;
+      if (xok) w.c = row[x];
+      if (edge) w.e = row[xe];
+    }
+    return w;
+  };
+  auto rowop = [&](const RowRaw& w, double2& Mu, double2& Ku) {
+    double2 l = make_double2(__shfl_up(w.c.x, 1), __shfl_up(w.c.y, 1));
+    double2 r = make_double2(__shfl_down(w.c.x, 1), __shfl_down(w.c.y, 1));
+    if (lane == 0) l = w.e;
+    if (lane == 63) r = w.e;
+    Mu = make_double2(mL * l.x + mC * w.c.x + mR * r.x, mL * l.y + mC * w.c.y + mR * r.y);
+    Ku = cfma(kL, l, cfma(kC, w.c, cmul(kR, r)));
+  };
+  double2 Mp, Kp, Mc, Kc;
+  rowop(load(r0 - 1), Mp, Kp);
+  rowop(load(r0), Mc, Kc);
+  RowRaw nx = load(r0 + 1);
+  double sr = 0.0, sf = 0.0;
+  for (int i = r0; i < r1; ++i) {
+    const RowRaw nn = load(i + 2);  // in flight while row i is combined
+    const double2 fv = xok ? a.f[off + (int64_t)i * n2 + x] : make_double2(0, 0);
+    double2 Mn, Kn;
+    rowop(nx, Mn, Kn);
+    double2 au = make_double2(0, 0);
+    const double2* Ms[3] = {&Mp, &Mc, &Mn};
+    const double2* Ks[3] = {&Kp, &Kc, &Kn};
+#pragma unroll
+    for (int o = -1; o <= 1; ++o) {
+      const double m1 = m1d(n1, A1.h, i, o);
+      const double2 k1 = k1d(n1, A1.h, A1.kLo, A1.kHi, i, o);
+      const double2 s1 = make_double2(k1.x - a.w2 * m1, k1.y);
+      au = cadd(cfma(s1, *Ms[o + 1], au), cscale(*Ks[o + 1], m1));
+    }
+    if (xok) {
+      const double2 r = csub(fv, au);
+      if (a.r) reinterpret_cast<TR*>(a.r)[off + (int64_t)i * n2 + x] = from_d2<TR>(r);
+      sr += r.x * r.x + r.y * r.y;
+      sf += fv.x * fv.x + fv.y * fv.y;
+    }
+    Mp = Mc;
+    Kp = Kc;
+    Mc = Mn;
+    Kc = Kn;
+    nx = nn;
+  }
+  red[0][threadIdx.x] = sr;
+  red[1][threadIdx.x] = sf;
+  __syncthreads();
+  for (int st = kResThreads / 2; st > 0; st >>= 1) {
+    if (threadIdx.x < st) {
+      red[0][threadIdx.x] += red[0][threadIdx.x + st];
+      red[1][threadIdx.x] += red[1][threadIdx.x + st];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    a.scratch[2 * bid] = red[0][0];
+    a.scratch[2 * bid + 1] = red[1][0];
+  }
+}
+
+// 3D: a block of 8 waves owns an (x_2, x_3) tile of 8 rows x 64 columns and
+// streams along x_1 over a strip of kStrip planes.  For every plane it loads
+// the 10 rows the tile needs (one halo row each side; lanes on consecutive
+// x_3), applies the x_3 operators M_3, K_3 (neighbours from adjacent lanes)
+// and parks them in LDS; each thread then forms the plane operators
+//   P = (M_2 (x) M_3) u_j,  Q = (K_2 (x) M_3 + M_2 (x) K_3) u_j
+// at its point, and the x_1 combination
+//   (A u)_i = sum_{o1} (K_1 - w^2 M_1)(i, o1) P_{i+o1} + M_1(i, o1) Q_{i+o1}
+// uses the P, Q of three consecutive planes kept in registers.  u is read
+// about 1.3 times (halo rows and planes), f once.
+constexpr int k3Rows = 8;
+constexpr int k3Threads = 64 * k3Rows;
+constexpr int k3Load = k3Rows + 2;
+
+template <typename TR>
+__global__ __launch_bounds__(k3Threads) void residual3d_kernel(ResidArgs a, int64_t xtiles, int64_t ytiles,
+                                                               int64_t blocks_per_rhs) {
+  __shared__ double2 Mx[2][k3Load][64];
+  __shared__ double2 Kx[2][k3Load][64];
+  __shared__ double red[2][k3Threads];
+  if (a.skip && *a.skip) return;
+  const int64_t bid = xcd_contiguous(blockIdx.x, gridDim.x);
+  const int64_t b = bid / blocks_per_rhs;
+  int64_t rem = bid - b * blocks_per_rhs;
+  const int64_t xi = rem % xtiles;
+  rem /= xtiles;
+  const int64_t yi = rem % ytiles;
+  const int64_t si = rem / ytiles;
+  const AxisOp& A1 = a.ax[0];
+  const AxisOp& A2 = a.ax[1];
+  const AxisOp& A3 = a.ax[2];
+  const int n1 = A1.n, n2 = A2.n, n3 = A3.n;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int x = (int)xi * 64 + lane;
+  const bool xok = x < n3;
+  const int y0 = (int)yi * k3Rows;      // first output row (x_2) of the tile
+  const int y = y0 + wv;                // this thread's output row
+  const bool yok = y < n2;
+  const int r0 = (int)si * kStrip, r1 = min(n1, r0 + kStrip);
+  const int64_t plane = (int64_t)n2 * n3;
+  const int64_t off = b * (int64_t)n1 * plane;
+  const double2* U = a.u + off;
+  const int xe = lane == 0 ? x - 1 : x + 1;
+  const bool edge = (lane == 0 || lane == 63) && xe >= 0 && xe < n3;
+  const double m3L = m1d(n3, A3.h, x, -1), m3C = m1d(n3, A3.h, x, 0), m3R = m1d(n3, A3.h, x, 1);
+  const double2 k3L = k1d(n3, A3.h, A3.kLo, A3.kHi, x, -1), k3C = k1d(n3, A3.h, A3.kLo, A3.kHi, x, 0),
+                k3R = k1d(n3, A3.h, A3.kLo, A3.kHi, x, 1);
+  // x_2 coefficients of this thread's output row
+  double m2[3];
+  double2 k2[3];
+#pragma unroll
+  for (int o = -1; o <= 1; ++o) {
+    m2[o + 1] = yok ? m1d(n2, A2.h, y, o) : 0.0;
+    k2[o + 1] = yok ? k1d(n2, A2.h, A2.kLo, A2.kHi, y, o) : make_double2(0, 0);
+  }
+  // plane j -> (P, Q) at this thread's point; buffer `buf` of the LDS rows
+  auto plane_op = [&](int j, int buf, double2& P, double2& Q) {
+    // rows y0 - 1 + rr, rr < k3Load, loaded by wave rr % k3Rows
+    for (int rr = wv; rr < k3Load; rr += k3Rows) {
+      const int yy = y0 - 1 + rr;
+      double2 c = make_double2(0, 0), e = make_double2(0, 0);
+      if (j >= 0 && j < n1 && yy >= 0 && yy < n2) {
+        const double2* row = U + (int64_t)j * plane + (int64_t)yy * n3;
+        if (xok) c = row[x];
+        if (edge) e = row[xe];
+      }
+      double2 l = make_double2(__shfl_up(c.x, 1), __shfl_up(c.y, 1));
+      double2 r = make_double2(__shfl_down(c.x, 1), __shfl_down(c.y, 1));
+      if (lane == 0) l = e;
+      if (lane == 63) r = e;
+      Mx[buf][rr][lane] = make_double2(m3L * l.x + m3C * c.x + m3R * r.x, m3L * l.y + m3C * c.y + m3R * r.y);
+      Kx[buf][rr][lane] = cfma(k3L, l, cfma(k3C, c, cmul(k3R, r)));
+    }
+    __syncthreads();
+    P = make_double2(0, 0);
+    Q = make_double2(0, 0);
+#pragma unroll
+    for (int o = -1; o <= 1; ++o) {
+      const double2 mv = Mx[buf][wv + 1 + o][lane], kv = Kx[buf][wv + 1 + o][lane];
+      P = cadd(P, cscale(mv, m2[o + 1]));
+      Q = cadd(Q, cadd(cmul(k2[o + 1], mv), cscale(kv, m2[o + 1])));
+    }
+  };
+  double2 Pp, Qp, Pc, Qc;
+  plane_op(r0 - 1, 0, Pp, Qp);
+  plane_op(r0, 1, Pc, Qc);
+  double sr = 0.0, sf = 0.0;
+  int buf = 0;
+  for (int i = r0; i < r1; ++i) {
+    const bool ok = xok && yok;
+    const int64_t idx = off + (int64_t)i * plane + (int64_t)y * n3 + x;
+    const double2 fv = ok ? a.f[idx] : make_double2(0, 0);
+    double2 Pn, Qn;
+    plane_op(i + 1, buf, Pn, Qn);  // two LDS buffers alternate: the one read last is not overwritten
+    buf ^= 1;
+    double2 au = make_double2(0, 0);
+    const double2* Ps[3] = {&Pp, &Pc, &Pn};
+    const double2* Qs[3] = {&Qp, &Qc, &Qn};
+#pragma unroll
+    for (int o = -1; o <= 1; ++o) {
+      const double m1 = m1d(n1, A1.h, i, o);
+      const double2 k1 = k1d(n1, A1.h, A1.kLo, A1.kHi, i, o);
+      const double2 s1 = make_double2(k1.x - a.w2 * m1, k1.y);
+      au = cadd(cfma(s1, *Ps[o + 1], au), cscale(*Qs[o + 1], m1));
+    }
+    if (ok) {
+      const double2 r = csub(fv, au);
+      if (a.r) reinterpret_cast<TR*>(a.r)[idx] = from_d2<TR>(r);
+      sr += r.x * r.x + r.y * r.y;
+      sf += fv.x * fv.x + fv.y * fv.y;
+    }
+    Pp = Pc;
+    Qp = Qc;
+    Pc = Pn;
+    Qc = Qn;
+  }
+  red[0][threadIdx.x] = sr;
+  red[1][threadIdx.x] = sf;
+  __syncthreads();
+  for (int st = k3Threads / 2; st > 0; st >>= 1) {
+    if (threadIdx.x < st) {
+      red[0][threadIdx.x] += red[0][threadIdx.x + st];
+      red[1][threadIdx.x] += red[1][threadIdx.x + st];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    a.scratch[2 * bid] = red[0][0];
+    a.scratch[2 * bid + 1] = red[1][0];
   }
 }
 
@@ -177,9 +424,31 @@ void geometry(int dim, const int64_t* n, int64_t* per, int64_t* quads, int64_t* 
 
 }  // namespace
 
+// 2D streaming geometry: column tiles of 256 and strips of kStrip rows.
+void geometry2d(const int64_t* n, int64_t* xtiles, int64_t* bpr) {
+  *xtiles = (n[1] + kResThreads - 1) / kResThreads;
+  *bpr = *xtiles * ((n[0] + kStrip - 1) / kStrip);
+}
+
+// 3D streaming geometry: 64-column x 8-row tiles, strips of kStrip planes.
+void geometry3d(const int64_t* n, int64_t* xtiles, int64_t* ytiles, int64_t* bpr) {
+  *xtiles = (n[2] + 63) / 64;
+  *ytiles = (n[1] + k3Rows - 1) / k3Rows;
+  *bpr = *xtiles * *ytiles * ((n[0] + kStrip - 1) / kStrip);
+}
+
 int64_t residual_scratch_len(int dim, const int64_t* grid, int nb) {
   int64_t per, quads, bpr;
   geometry(dim, grid, &per, &quads, &bpr);
+  if (dim == 2) {
+    int64_t xt, b2;
+    geometry2d(grid, &xt, &b2);
+    bpr = std::max(bpr, b2);
+  } else {
+    int64_t xt, yt, b3;
+    geometry3d(grid, &xt, &yt, &b3);
+    bpr = std::max(bpr, b3);
+  }
   return 2 * bpr * nb;
 }
 
@@ -187,6 +456,36 @@ hipError_t launch_residual(const ResidArgs& a, hipStream_t s) {
   int64_t n[3];
   for (int j = 0; j < a.dim; ++j) n[j] = a.ax[j].n;
   int64_t per, quads, bpr;
+  if (a.dim == 2) {
+    int64_t xt;
+    geometry2d(n, &xt, &bpr);
+    const int64_t blocks = bpr * a.nb;
+    if (blocks > 0x7fffffffLL || 2 * blocks > a.scratch_len) return hipErrorInvalidValue;
+    if (a.r_kind == ST_C64)
+      hipLaunchKernelGGL(residual2d_kernel<float2>, dim3((unsigned)blocks), dim3(kResThreads), 0, s, a, xt, bpr);
+    else
+      hipLaunchKernelGGL(residual2d_kernel<double2>, dim3((unsigned)blocks), dim3(kResThreads), 0, s, a, xt, bpr);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(norm_finish_kernel, dim3((unsigned)a.nb), dim3(kFinThreads), 0, s, a.scratch, bpr, a.norms,
+                       a.skip);
+    return hipGetLastError();
+  }
+  {
+    int64_t xt, yt;
+    geometry3d(n, &xt, &yt, &bpr);
+    const int64_t blocks = bpr * a.nb;
+    if (blocks > 0x7fffffffLL || 2 * blocks > a.scratch_len) return hipErrorInvalidValue;
+    if (a.r_kind == ST_C64)
+      hipLaunchKernelGGL(residual3d_kernel<float2>, dim3((unsigned)blocks), dim3(k3Threads), 0, s, a, xt, yt, bpr);
+    else
+      hipLaunchKernelGGL(residual3d_kernel<double2>, dim3((unsigned)blocks), dim3(k3Threads), 0, s, a, xt, yt, bpr);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(norm_finish_kernel, dim3((unsigned)a.nb), dim3(kFinThreads), 0, s, a.scratch, bpr, a.norms,
+                       a.skip);
+    return hipGetLastError();
+  }
   geometry(a.dim, n, &per, &quads, &bpr);
   const int64_t blocks = bpr * a.nb;
   if (blocks > 0x7fffffffLL || 2 * blocks > a.scratch_len) return hipErrorInvalidValue;
