@@ -108,31 +108,100 @@ __device__ inline Aff shfl_down_aff(const Aff& a, int d, int w) {
   return o;
 }
 
+// Moves of a 64-bit value across lanes with the data-parallel primitives:
+// lanes whose source lane is outside the pattern (or whose row is masked
+// off) keep `old`.
+template <int CTRL, int ROWMASK>
+__device__ inline double dpp_d(double src, double old) {
+  const unsigned long long s = __builtin_bit_cast(unsigned long long, src);
+  const unsigned long long o = __builtin_bit_cast(unsigned long long, old);
+  const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp((int)(unsigned)o, (int)(unsigned)s, CTRL, ROWMASK, 0xF, false);
+  const unsigned hi = (unsigned)__builtin_amdgcn_update_dpp((int)(unsigned)(o >> 32), (int)(unsigned)(s >> 32), CTRL,
+                                                            ROWMASK, 0xF, false);
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+template <int CTRL, int ROWMASK = 0xF>
+__device__ inline Aff dpp_aff(const Aff& v) {  // identity where nothing arrives
+  Aff o;
+  o.f.x = dpp_d<CTRL, ROWMASK>(v.f.x, 1.0);
+  o.f.y = dpp_d<CTRL, ROWMASK>(v.f.y, 0.0);
+  o.g.x = dpp_d<CTRL, ROWMASK>(v.g.x, 0.0);
+  o.g.y = dpp_d<CTRL, ROWMASK>(v.g.y, 0.0);
+  return o;
+}
+// DPP controls (GFX9 encoding): row_shr:n = 0x110 + n, row_bcast:15 = 0x142,
+// row_bcast:31 = 0x143, wave_shr:1 = 0x138.
+constexpr int kRowShr1 = 0x111, kRowShr2 = 0x112, kRowShr4 = 0x114, kRowShr8 = 0x118;
+constexpr int kRowBcast15 = 0x142, kRowBcast31 = 0x143, kWaveShr1 = 0x138;
+
+// Inclusive prefix composition within groups of W lanes (W = 16, 32 or 64;
+// later lanes applied after earlier ones): four in-row steps, then the row
+// broadcasts that carry row totals to the following rows.
+template <int W>
+__device__ inline Aff dpp_inclusive(Aff v) {
+  v = aff_then(v, dpp_aff<kRowShr1>(v));
+  v = aff_then(v, dpp_aff<kRowShr2>(v));
+  v = aff_then(v, dpp_aff<kRowShr4>(v));
+  v = aff_then(v, dpp_aff<kRowShr8>(v));
+  if constexpr (W >= 32) v = aff_then(v, dpp_aff<kRowBcast15, 0xA>(v));
+  if constexpr (W >= 64) v = aff_then(v, dpp_aff<kRowBcast31, 0xC>(v));
+  return v;
+}
+
+// Lane r of each group of W lanes takes the value of lane W - 1 - r.
+template <int W>
+__device__ inline Aff reverse_aff(const Aff& v) {
+  const int lane = threadIdx.x & 63;
+  const int src = (lane & ~(W - 1)) + (W - 1 - (lane & (W - 1)));
+  Aff o;
+  o.f = make_double2(__shfl(v.f.x, src), __shfl(v.f.y, src));
+  o.g = make_double2(__shfl(v.g.x, src), __shfl(v.g.y, src));
+  return o;
+}
+
 // Exclusive scans of affine maps over the P lanes of a line (lanes
 // [slot*P, slot*P + P) of the block).  Forward: lane q receives
-// A_{q-1} o ... o A_0; backward: lane q receives A_{q+1} o ... o A_{P-1}.
-// For P > 64 the waves of a line exchange their totals through LDS (`wbuf`,
-// NT/64 entries); every thread of the block must call these.
+// A_{q-1} o ... o A_0; backward: lane q receives A_{q+1} o ... o A_{P-1}
+// (the forward scan in reversed lane order).  Whole waves (P >= 64) use DPP
+// moves; lines of fewer lanes use shuffles.  For P > 64 the
+// waves of a line exchange their totals through LDS (`wbuf`, NT/64 entries;
+// forward and backward scans use different buffers, so one barrier per scan
+// suffices: the next write to a buffer follows the other scan's barrier).
+// Every thread of the block must call these.
+template <int P>
+__device__ inline Aff wave_scan_excl(Aff v, int q, Aff& incl) {
+  constexpr int W = P < 64 ? P : 64;
+  Aff ex;
+  if constexpr (W == 64) {
+    v = dpp_inclusive<64>(v);
+    incl = v;
+    ex = dpp_aff<kWaveShr1>(v);
+  } else {
+    const int lq = q & (W - 1);
+#pragma unroll
+    for (int d = 1; d < W; d <<= 1) {
+      const Aff o = shfl_up_aff(v, d, W);
+      if (lq >= d) v = aff_then(v, o);
+    }
+    incl = v;
+    ex = shfl_up_aff(v, 1, W);
+    if (lq == 0) ex = aff_ident();
+  }
+  return ex;
+}
+
 template <int P>
 __device__ inline Aff scan_fwd(Aff v, int q, Aff* wbuf) {
-  constexpr int W = P < 64 ? P : 64;
-  const int lq = q & (W - 1);
-#pragma unroll
-  for (int d = 1; d < W; d <<= 1) {
-    const Aff o = shfl_up_aff(v, d, W);
-    if (lq >= d) v = aff_then(v, o);
-  }
-  Aff ex = shfl_up_aff(v, 1, W);
-  if (lq == 0) ex = aff_ident();
+  Aff incl;
+  Aff ex = wave_scan_excl<P>(v, q, incl);
   if constexpr (P > 64) {
     const int wv = threadIdx.x >> 6;          // wave in block
     const int w0 = wv - (q >> 6);             // first wave of this line
-    if (lq == 63) wbuf[wv] = v;               // inclusive wave total
+    if ((q & 63) == 63) wbuf[wv] = incl;      // inclusive wave total
     __syncthreads();
     Aff pre = aff_ident();
     for (int w = w0; w < wv; ++w) pre = aff_then(wbuf[w], pre);
     ex = aff_then(ex, pre);
-    __syncthreads();
   }
   return ex;
 }
@@ -140,23 +209,30 @@ __device__ inline Aff scan_fwd(Aff v, int q, Aff* wbuf) {
 template <int P>
 __device__ inline Aff scan_bwd(Aff v, int q, Aff* wbuf) {
   constexpr int W = P < 64 ? P : 64;
-  const int lq = q & (W - 1);
+  Aff ex, incl;
+  if constexpr (W == 64) {
+    // reversed lane order turns the suffix scan into a prefix scan of the
+    // same operator over the physical lane positions; in reversed order the
+    // last lane holds the composition of the whole wave
+    ex = reverse_aff<64>(wave_scan_excl<P>(reverse_aff<64>(v), q, incl));
+  } else {
+    const int lq = q & (W - 1);
 #pragma unroll
-  for (int d = 1; d < W; d <<= 1) {
-    const Aff o = shfl_down_aff(v, d, W);
-    if (lq + d < W) v = aff_then(v, o);
+    for (int d = 1; d < W; d <<= 1) {
+      const Aff o = shfl_down_aff(v, d, W);
+      if (lq + d < W) v = aff_then(v, o);
+    }
+    ex = shfl_down_aff(v, 1, W);
+    if (lq == W - 1) ex = aff_ident();
   }
-  Aff ex = shfl_down_aff(v, 1, W);
-  if (lq == W - 1) ex = aff_ident();
   if constexpr (P > 64) {
     const int wv = threadIdx.x >> 6;
-    const int wl = wv - (q >> 6) + P / 64 - 1;  // last wave of this line
-    if (lq == 0) wbuf[wv] = v;                  // inclusive suffix total of the wave
+    const int wl = wv - (q >> 6) + P / 64 - 1;       // last wave of this line
+    if ((threadIdx.x & 63) == 63) wbuf[wv] = incl;   // inclusive suffix total of the wave
     __syncthreads();
     Aff suf = aff_ident();
     for (int w = wl; w > wv; --w) suf = aff_then(wbuf[w], suf);
     ex = aff_then(ex, suf);
-    __syncthreads();
   }
   return ex;
 }
@@ -267,7 +343,7 @@ __global__ __launch_bounds__(NT) void lines_kernel(LineDev a) {
   constexpr int SPW = 64 / PW;            // lines per wave
   constexpr int LPB = NT / P;             // lines per block
   constexpr bool FIXED = C > 0;
-  __shared__ Aff wbuf[NW + 1];
+  __shared__ Aff wbuf[2][NW + 1];         // wave totals of the forward / backward scans
   extern __shared__ double2 stage[];      // NW areas of 72 c padded values
   if (a.skip && *a.skip) return;
 
@@ -299,10 +375,10 @@ __global__ __launch_bounds__(NT) void lines_kernel(LineDev a) {
     for (int j = 0; j < kCMax; ++j) acc0[j] = acc1[j] = make_double2(0, 0);
   }
 
-  // Reducing launches whose lines span whole waves (P >= 64) prefetch the
+  // Reducing launches with one line per block (P >= 256) prefetch the
   // next line's input rows into registers while the current line is solved,
   // so the load latency overlaps the sweeps.
-  constexpr bool PREF = P >= 64 && RED;
+  constexpr bool PREF = P >= 256 && RED;
   T pre[PREF ? kCMax : 1];
   auto fetch = [&](int itn) {
     uint32_t sb, sl, sm;
@@ -428,7 +504,7 @@ __global__ __launch_bounds__(NT) void lines_kernel(LineDev a) {
         }
       }
     }
-    const Aff Ein = scan_fwd<P>(A, q, wbuf);
+    const Aff Ein = scan_fwd<P>(A, q, wbuf[0]);
 
     // ---- 2. forward values, scaled for the back substitution --------------
     // h_x = z_x / p_x; the lane's slots now take the backward multipliers
@@ -460,7 +536,7 @@ __global__ __launch_bounds__(NT) void lines_kernel(LineDev a) {
         B.g = cfma(gx, B.g, z[j]);
       }
     }
-    const Aff Bin = scan_bwd<P>(B, q, wbuf);
+    const Aff Bin = scan_bwd<P>(B, q, wbuf[1]);
     {
       double2 ynext = Bin.g;
 #pragma unroll
