@@ -155,10 +155,12 @@ constexpr int nstages(int L) { return ilog2(L) / 3 + (ilog2(L) % 3 ? 1 : 0); }
 constexpr int radix_of(int L, int s) {
   return (ilog2(L) % 3 && s == 0) ? (ilog2(L) % 3 == 1 ? 2 : 4) : 8;
 }
-// Columns per tile: an LDS tile of L x W complex values (at most kFftLdsBytes),
-// W <= kFftMaxW.  32 KB tiles keep several blocks resident per compute unit.
+// Columns per tile: an LDS tile of L x W complex values, W <= kFftMaxW.
+// 32 KB tiles keep several blocks resident per compute unit; the longest
+// passes (L = 512) take 64 KB so that each row segment stays >= 128 bytes.
+constexpr int tile_bytes(int L) { return L >= 512 ? 2 * kFftLdsBytes : kFftLdsBytes; }
 template <typename C> constexpr int tile_w(int L) {
-  return (kFftLdsBytes / (L * (int)sizeof(C))) < kFftMaxW ? kFftLdsBytes / (L * (int)sizeof(C)) : kFftMaxW;
+  return (tile_bytes(L) / (L * (int)sizeof(C))) < kFftMaxW ? tile_bytes(L) / (L * (int)sizeof(C)) : kFftMaxW;
 }
 
 // One Stockham stage of radix R with Ns points already combined.  Thread
