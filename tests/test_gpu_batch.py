@@ -108,3 +108,34 @@ def test_batch_reports_nonfinite_problem():
     batch.close()
     for p in plans:
         p.close()
+
+
+def test_batch_uneven_sides_vs_banded_lu():
+    """Problems shaped like the uneven batch (sides 2^k + 1, 8-20 points per
+    wavelength, 4 right-hand sides, mixed precision, autotuned transform),
+    against banded LU where it is affordable (sides up to 257)."""
+    probs = [((257, 257), inputs.omega_for_ppw(257, 9.5)), ((129, 129), inputs.omega_for_ppw(129, 17.0)),
+             ((65, 65), inputs.omega_for_ppw(65, 12.0))]
+    plans, fs, us, hosts = [], [], [], []
+    for i, (grid, omega) in enumerate(probs):
+        plans.append(helm.Plan(grid, inputs.spacing(grid), omega, precision=helm.PREC_MIXED,
+                               transform=helm.TRANSFORM_AUTO))
+        f = inputs.gaussian_batch(grid, [inputs.rhs_seed(4, 50 + i, r) for r in range(4)])
+        hosts.append(f)
+        fs.append(torch.from_numpy(f).cuda())
+        us.append(torch.empty_like(fs[-1]))
+    batch = helm.Batch(plans, max_nrhs=4)
+    batch.solve(fs, us)
+    for i, (grid, omega) in enumerate(probs):
+        rep = batch.report(i)
+        h = inputs.spacing(grid)
+        ref = fem.solve(grid, h, omega, ((True, True), (True, True)), hosts[i].reshape(4, -1))
+        u = us[i].cpu().numpy().reshape(4, -1)
+        err = fem.rel_error(u, ref)
+        res = fem.rel_residual(grid, h, omega, ((True, True), (True, True)), u, hosts[i].reshape(4, -1))
+        _say(f"  {grid}: transform {rep['transform']} err {np.max(err):.2e} res {np.max(res):.2e} {rep}")
+        assert rep["status"] == helm.HELM_OK
+        assert np.max(res) <= 1e-10 and np.max(err) <= 1e-8
+    batch.close()
+    for p in plans:
+        p.close()
