@@ -69,6 +69,16 @@ def _traffic(kernel, workload, calls_per_step):
     return rec.get("bytes_per_launch")
 
 
+def describe(name, wl):
+    grid, dim = wl["grid"], len(wl["grid"])
+    load = ("seeded Gaussian complex" if wl["rhs"] == "gaussian" else
+            "Gaussian complex plus a centre point source" if wl["rhs"] == "gaussian+point" else
+            "paper load (0.01 on the first n1 entries, 1 elsewhere)")
+    return (f"{name}: {dim}D {'bilinear Q1' if dim == 2 else 'trilinear Q1'} FE Helmholtz "
+            f"{'x'.join(str(n) for n in grid)} nodes, unit {'square' if dim == 2 else 'cube'}, "
+            f"first-order ABC on all faces, omega={wl['omega']:.6f}, {wl['nrhs']} {load} RHS, FP64")
+
+
 def cpu_baseline():
     """The oracle (banded LU, zgbsv, complex128) on a 720 x 720 sample of the
     same problem family: 10 points per wavelength, absorbing on all faces,
@@ -207,8 +217,11 @@ def main():
     for n in grid:
         N *= n
     _log(f"workload {args.workload}: grid {grid} omega {omega:.4f} nrhs {nrhs}")
-    seeds = [inputs.rhs_seed(wl["config"], 0, r) for r in range(nrhs)]
-    f = inputs.gaussian_device(grid, seeds, "cuda")
+    if wl["rhs"] == "paper":
+        f = torch.from_numpy(inputs.paper_rhs(grid)[None]).to("cuda")
+    else:
+        seeds = [inputs.rhs_seed(wl["config"], 0, r) for r in range(nrhs)]
+        f = inputs.gaussian_device(grid, seeds, "cuda")
     u = torch.empty_like(f)
 
     plan = helm.Plan(grid, h, omega, mask, precision=helm.PREC_FP64, check=True)
@@ -306,10 +319,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"{args.workload}: 2D bilinear Q1 Helmholtz {grid[0]}x{grid[1]} nodes, "
-                               f"unit square, first-order ABC on all faces, omega={omega:.6f} "
-                               f"(10 points/wavelength), {nrhs} seeded Gaussian complex RHS, FP64"
-                   if len(grid) == 2 else args.workload,
+        "config": {"workload": describe(args.workload, wl),
                    "rel_residual": rep["rel_residual_max"], "refinement_steps": rep["iterations"]},
         "roofline": roofline,
         "mixed": mixed,

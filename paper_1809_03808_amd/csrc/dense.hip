@@ -15,8 +15,9 @@
 // is a complex GEMM C = Q^T B evaluated with real 16x16x4 MFMA tiles
 // (four real products per complex one).  A 256-thread block computes a 64 x 64
 // output tile; each wave owns a 32 x 32 quarter (2 x 2 MFMA tiles, real and
-// imaginary accumulators).  K steps of 16 are staged through LDS in planar
-// (real / imaginary) form, padded against bank conflicts.
+// imaginary accumulators).  K steps of 16 are staged through two LDS buffers
+// in planar (real / imaginary) form, padded against bank conflicts, with the
+// next step's global loads in flight during the current step's products.
 #include "helm_internal.h"
 
 namespace helm {
@@ -52,7 +53,7 @@ template <typename R, typename TIN, typename TOUT>
 __global__ __launch_bounds__(256) void dense_kernel(DenseArgs a) {
   using M = Mma<R>;
   using acc = typename M::acc;
-  __shared__ R Ar[kBK][kBM + kPad], Ai[kBK][kBM + kPad], Br[kBK][kBN + kPad], Bi[kBK][kBN + kPad];
+  __shared__ R Ar[2][kBK][kBM + kPad], Ai[2][kBK][kBM + kPad], Br[2][kBK][kBN + kPad], Bi[2][kBK][kBN + kPad];
   if (a.skip && *a.skip) return;
   const int n = a.n;
   const int64_t S = a.S;
@@ -79,47 +80,68 @@ __global__ __launch_bounds__(256) void dense_kernel(DenseArgs a) {
       ci[t][u] = acc{0, 0, 0, 0};
     }
 
+  // Software pipeline: the global loads of K tile k + 1 are issued into
+  // registers before the products of tile k, then parked in the other LDS
+  // buffer; one barrier per tile separates the writes of a buffer from the
+  // reads of it two tiles earlier.
+  constexpr int kPer = kBK * kBM / 256;  // elements of each operand tile per thread
+  R qa[kPer][2], qb[kPer][2];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int t = 0; t < kPer; ++t) {
+      const int e = (int)threadIdx.x + 256 * t;
+      {  // A[m][k] = Q[k][m], rows k of Q are contiguous in m
+        const int kk = e / kBM, mm = e % kBM;
+        const int i = k0 + kk, m = m0 + mm;
+        qa[t][0] = 0;
+        qa[t][1] = 0;
+        if (i < n && m < n) {
+          qa[t][0] = Q[2 * ((int64_t)i * n + m)];
+          qa[t][1] = Q[2 * ((int64_t)i * n + m) + 1];
+        }
+      }
+      {  // B: rows k of the input block, contiguous in x
+        const int kk = e / kBN, xx = e % kBN;
+        const int i = k0 + kk;
+        const int64_t x = x0 + xx;
+        qb[t][0] = 0;
+        qb[t][1] = 0;
+        if (i < n && x < S) {
+          const TIN v = in[(int64_t)i * S + x];
+          qb[t][0] = (R)v.x;
+          qb[t][1] = (R)v.y;
+        }
+      }
+    }
+  };
+  auto park = [&](int buf) {
+#pragma unroll
+    for (int t = 0; t < kPer; ++t) {
+      const int e = (int)threadIdx.x + 256 * t;
+      Ar[buf][e / kBM][e % kBM] = qa[t][0];
+      Ai[buf][e / kBM][e % kBM] = qa[t][1];
+      Br[buf][e / kBN][e % kBN] = qb[t][0];
+      Bi[buf][e / kBN][e % kBN] = qb[t][1];
+    }
+  };
+  fetch(0);
+  park(0);
+  __syncthreads();
+  int buf = 0;
   for (int k0 = 0; k0 < n; k0 += kBK) {
-    // A tile: A[m][k] = Q[k][m], rows k of Q are contiguous in m
-#pragma unroll
-    for (int e = tid; e < kBK * kBM; e += 256) {
-      const int kk = e / kBM, mm = e % kBM;
-      const int i = k0 + kk, m = m0 + mm;
-      R qr = 0, qi = 0;
-      if (i < n && m < n) {
-        qr = Q[2 * ((int64_t)i * n + m)];
-        qi = Q[2 * ((int64_t)i * n + m) + 1];
-      }
-      Ar[kk][mm] = qr;
-      Ai[kk][mm] = qi;
-    }
-    // B tile: rows k of the input block, contiguous in x
-#pragma unroll
-    for (int e = tid; e < kBK * kBN; e += 256) {
-      const int kk = e / kBN, xx = e % kBN;
-      const int i = k0 + kk;
-      const int64_t x = x0 + xx;
-      R vr = 0, vi = 0;
-      if (i < n && x < S) {
-        const TIN v = in[(int64_t)i * S + x];
-        vr = (R)v.x;
-        vi = (R)v.y;
-      }
-      Br[kk][xx] = vr;
-      Bi[kk][xx] = vi;
-    }
-    __syncthreads();
+    const bool more = k0 + kBK < n;
+    if (more) fetch(k0 + kBK);
 #pragma unroll
     for (int ks = 0; ks < kBK; ks += 4) {
       const int kl = ks + lane / 16, c16 = lane % 16;
       R ar[2], ai[2], an[2], br[2], bi[2];
 #pragma unroll
       for (int t = 0; t < 2; ++t) {
-        ar[t] = Ar[kl][wm + 16 * t + c16];
-        ai[t] = Ai[kl][wm + 16 * t + c16];
+        ar[t] = Ar[buf][kl][wm + 16 * t + c16];
+        ai[t] = Ai[buf][kl][wm + 16 * t + c16];
         an[t] = -ai[t];
-        br[t] = Br[kl][wn + 16 * t + c16];
-        bi[t] = Bi[kl][wn + 16 * t + c16];
+        br[t] = Br[buf][kl][wn + 16 * t + c16];
+        bi[t] = Bi[buf][kl][wn + 16 * t + c16];
       }
 #pragma unroll
       for (int t = 0; t < 2; ++t)
@@ -131,7 +153,9 @@ __global__ __launch_bounds__(256) void dense_kernel(DenseArgs a) {
           ci[t][u] = M::op(ai[t], br[u], ci[t][u]);
         }
     }
+    if (more) park(buf ^ 1);
     __syncthreads();
+    buf ^= 1;
   }
 
   TOUT* out = reinterpret_cast<TOUT*>(a.out) + beta * (int64_t)n * S;

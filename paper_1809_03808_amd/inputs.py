@@ -105,6 +105,12 @@ def workload(name):
     if name == "3d_512_ppw10_x16":
         return dict(dim=3, grid=(512, 512, 512), omega=TWO_PI * 51.1, nrhs=16, config=5,
                     rhs="gaussian")
+    # the largest shapes of the paper's own experiments (Section 6): omega = 2 pi,
+    # n = 2^k + 1, its deterministic load
+    if name == "paper_2d_2049":
+        return dict(dim=2, grid=(2049, 2049), omega=TWO_PI, nrhs=1, config=6, rhs="paper")
+    if name == "paper_3d_513":
+        return dict(dim=3, grid=(513, 513, 513), omega=TWO_PI, nrhs=1, config=7, rhs="paper")
     raise KeyError(name)
 
 
