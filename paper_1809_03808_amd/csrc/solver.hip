@@ -1423,6 +1423,16 @@ int helm_setup(int dim, const int64_t* grid, const double* h, double omega, uint
     p->grid[j] = grid[j];
     p->h[j] = h[j];
   }
+  // size limits of this build, checked before any device call: line axis
+  // <= 4096 nodes (at most 512 lanes of 8 rows), periodised lengths whose
+  // transform splits into two passes of <= 512 (power of two <= 2^18, or a
+  // chirp-z convolution length <= 2^18)
+  if (grid[last] > 4096) return HELM_EUNSUPPORTED;
+  for (int j = 0; j < dim - 1; ++j) {
+    int64_t M = 1;
+    while (M < (is_pow2(grid[j]) ? grid[j] : 2 * grid[j] - 1)) M <<= 1;
+    if (M > 512 * 512) return HELM_EUNSUPPORTED;
+  }
   if (hipGetDevice(&p->device) != hipSuccess) return HELM_EDEVICE;
   p->nper = dim - 1;
   p->nL = (int)grid[last];

@@ -82,3 +82,14 @@ def test_dense_transform_size_limit():
     with pytest.raises(helm.HelmError) as e:
         helm.Plan((16, 16), (1 / 15, 1 / 15), 5.0, transform=7)
     assert e.value.code == helm.HELM_EINVAL
+
+
+@pytest.mark.parametrize("grid", [(16, 4097), (131073, 16), (262145, 16), (16, 140000, 9)])
+def test_setup_size_limits(grid):
+    """Lengths beyond this build's limits are refused before any device call:
+    a line axis above 4096 nodes, a periodised length whose transform would
+    need more than two passes of 512."""
+    h = tuple(1.0 / (n - 1) for n in grid)
+    with pytest.raises(helm.HelmError) as e:
+        helm.Plan(grid, h, 5.0)
+    assert e.value.code == helm.HELM_EUNSUPPORTED
