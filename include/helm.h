@@ -112,9 +112,16 @@ int helm_setup(int dim, const int64_t* grid, const double* h, double omega,
  *   f  device, read only, complex128 [nrhs][grid]
  *   u  device, written, complex128 [nrhs][grid]; must not overlap f
  * All kernels run on `stream`.  With checking (mixed precision, or FP64 with
- * opt.check = 1) the call synchronises `stream` once per refinement step to
- * read the residual norms; a plain FP64 solve (check = 0) is fully
- * asynchronous.  The plan's workspace grows on demand for larger nrhs; a plan
+ * opt.check = 1) the call synchronises `stream` to read the residual norms
+ * (once per refinement step on the host loop, once per call on a captured
+ * solve); a plain FP64 solve (check = 0) is fully asynchronous.  A call that
+ * repeats the previous call's arguments (f, u, nrhs, stream) captures the
+ * whole solve, with as many device-controlled refinement steps as the
+ * previous call took, into a HIP graph that later repeats launch; if those
+ * steps fall short of opt.tol the host loop continues and the next call
+ * captures again.  Results and the report are those of the host loop.
+ * Per-kernel profiling (helm_profile) always runs the host loop.  The plan's
+ * workspace grows on demand for larger nrhs (dropping captured graphs); a plan
  * must not be used from two streams at once.
  * Errors: HELM_EINVAL, HELM_ENOMEM, HELM_EDEVICE, HELM_ENOCONV (u holds the
  * last iterate), HELM_ENONFINITE (f holds NaN/Inf).

@@ -13,6 +13,7 @@
 // boundary reductions act on the inner solutions in x_2-mode space before a
 // two-plane inverse transform.
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -42,6 +43,9 @@ struct DevMem {
   }
   hipError_t ensure(size_t b) {
     if (b <= bytes && p) return hipSuccess;
+    // the old buffer may still be in use by queued work (a graph launched
+    // earlier, an asynchronous solve): let it drain before freeing
+    if (p) (void)hipDeviceSynchronize();
     release();
     if (b == 0) return hipSuccess;
     hipError_t e = hipMalloc(&p, b);
@@ -141,7 +145,38 @@ struct helm_plan {
   std::vector<Ev> evs;
   size_t nev = 0;
   helm_kernel_stats kst{};
+  // Workspace generation: raised whenever a workspace buffer moves, so that
+  // graphs captured on the old addresses are not launched again.
+  uint64_t ws_gen = 0;
+  // Captured solve for repeated helm_solve calls on unchanged arguments:
+  // the arguments of the previous call and the refinement steps it took,
+  // the graph with the arguments it was captured for, and a pinned host
+  // copy of the device refinement control written by its last launch.
+  struct Key {
+    const void* f = nullptr;
+    void* u = nullptr;
+    int nrhs = 0;
+    hipStream_t st = nullptr;
+    bool operator==(const Key& o) const { return f == o.f && u == o.u && nrhs == o.nrhs && st == o.st; }
+  };
+  Key last_key, graph_key;
+  int prev_steps = -1;
+  int graph_steps = 0;
+  uint64_t graph_gen = 0;
+  hipStream_t gcap = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  void* ctl_host = nullptr;
+  void drop_graph() {
+    if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    graph_exec = nullptr;
+    graph = nullptr;
+  }
   ~helm_plan() {
+    drop_graph();
+    if (gcap) (void)hipStreamDestroy(gcap);
+    if (ctl_host) (void)hipHostFree(ctl_host);
     for (auto& e : evs) {
       (void)hipEventDestroy(e.a);
       (void)hipEventDestroy(e.b);
@@ -977,7 +1012,24 @@ int64_t npoints(const helm_plan* p) {
   return n;
 }
 
+// Addresses of every workspace buffer a captured solve refers to.
+std::array<void*, 15> workspace_addrs(const helm_plan* p) {
+  return {p->W0.p, p->W1.p, p->W2.p, p->R.p, p->part.p, p->VB.p, p->PIb.p, p->P0.p,
+          p->P1.p, p->P2.p, p->P3.p, p->scratch.p, p->norms.p, p->BT1.p, p->ctl.p};
+}
+
+int ensure_workspace_impl(helm_plan* p, int nb, bool fp32, bool need_r);
+
+// Grows the workspace for nb right-hand sides; raises the plan's workspace
+// generation when any buffer moved.
 int ensure_workspace(helm_plan* p, int nb, bool fp32, bool need_r) {
+  const auto before = workspace_addrs(p);
+  const int rc = ensure_workspace_impl(p, nb, fp32, need_r);
+  if (workspace_addrs(p) != before) ++p->ws_gen;
+  return rc;
+}
+
+int ensure_workspace_impl(helm_plan* p, int nb, bool fp32, bool need_r) {
   const int64_t N = npoints(p);
   const size_t esz = fp32 ? sizeof(float2) : sizeof(double2);
   HCHK(p->W0.ensure((size_t)N * nb * esz));
@@ -1153,20 +1205,20 @@ struct IrCtl {
   double rel_last;
 };
 
-__global__ void ir_reset_kernel(IrCtl* c, int done) {
+__global__ void ir_reset_kernel(IrCtl* c, int done, IrCtl* mirror) {
   c->done = done;
   c->iters = 0;
   c->status = HELM_OK;
   c->pad = 0;
   c->rel_first = -1.0;
   c->rel_last = -1.0;
+  if (mirror) *mirror = *c;
 }
 
 // After the residual of stage k (k = 0: first solve): converged, failed or
 // one more refinement step.  Same rule as the host loop of helm_solve: stop
 // at tol, at max_iter steps, or when a step fails to halve the residual.
-__global__ void ir_check_kernel(const double* norms, int nb, double tol, int max_steps, int stage, IrCtl* c) {
-  if (c->done) return;
+__device__ void ir_update(const double* norms, int nb, double tol, int max_steps, int stage, IrCtl* c) {
   double mx = 0.0;
   bool bad = false;
   for (int b = 0; b < nb; ++b) {
@@ -1195,10 +1247,23 @@ __global__ void ir_check_kernel(const double* norms, int nb, double tol, int max
   }
 }
 
+// With `mirror` set, the resulting state is also written there (pinned host
+// memory that the host reads after the stream has drained).
+__global__ void ir_check_kernel(const double* norms, int nb, double tol, int max_steps, int stage, IrCtl* c,
+                                IrCtl* mirror) {
+  if (!c->done) ir_update(norms, nb, tol, max_steps, stage, c);
+  if (mirror) *mirror = *c;
+}
+
 // Enqueue one problem's complete solve with `steps` refinement steps whose
 // launches are skipped on the device once the residual criterion is met.
-// Nothing here allocates or synchronises (the workspace must be in place).
-int enqueue_device_ir(helm_plan* p, const double2* F, double2* U, int nb, int steps, hipStream_t st) {
+// `limit` is the step count at which the check declares non-convergence:
+// `steps` when the enqueued steps are all there will be, the plan's max_iter
+// when the host may continue after them (the control block is then left
+// not done).  Nothing here allocates or synchronises (the workspace must be
+// in place).
+int enqueue_device_ir(helm_plan* p, const double2* F, double2* U, int nb, int steps, int limit, IrCtl* mirror,
+                      hipStream_t st) {
   const bool mixed = p->opt.precision == HELM_PREC_MIXED;
   const bool check = mixed || p->opt.check;
   IrCtl* c = p->ctl.as<IrCtl>();
@@ -1207,7 +1272,7 @@ int enqueue_device_ir(helm_plan* p, const double2* F, double2* U, int nb, int st
   p->skip_cur = nullptr;
   int rc = HELM_OK;
   do {
-    hipLaunchKernelGGL(ir_reset_kernel, dim3(1), dim3(1), 0, st, c, check ? 0 : 1);
+    hipLaunchKernelGGL(ir_reset_kernel, dim3(1), dim3(1), 0, st, c, check ? 0 : 1, mirror);
     if (hipGetLastError() != hipSuccess) { rc = HELM_EDEVICE; break; }
     rc = solve_once(p, F, ST_C128, U, 0, nb, mixed, st);
     if (rc || !check) break;
@@ -1225,13 +1290,140 @@ int enqueue_device_ir(helm_plan* p, const double2* F, double2* U, int nb, int st
       a.r_kind = rk;
       if (launch_residual(a, st) != hipSuccess) { rc = HELM_EDEVICE; break; }
       hipLaunchKernelGGL(ir_check_kernel, dim3(1), dim3(1), 0, st, (const double*)a.norms, nb, p->opt.tol,
-                         steps, k, c);
+                         limit, k, c, mirror);
       if (hipGetLastError() != hipSuccess) rc = HELM_EDEVICE;
     }
   } while (false);
   p->skip_cur = nullptr;
   p->prof = prof;
   return rc;
+}
+
+// Capture the whole solve of (F, U, nb) with `steps` device-controlled
+// refinement steps into the plan's graph.  The capture runs on an internal
+// stream (the legacy default stream cannot be captured); the graph is
+// launched on the caller's stream.
+int capture_solve(helm_plan* p, const double2* F, double2* U, int nb, hipStream_t st, int steps) {
+  p->drop_graph();
+  if (!p->gcap && hipStreamCreateWithFlags(&p->gcap, hipStreamNonBlocking) != hipSuccess) return HELM_EDEVICE;
+  if (!p->ctl_host && hipHostMalloc(&p->ctl_host, sizeof(IrCtl), hipHostMallocDefault) != hipSuccess) {
+    p->ctl_host = nullptr;
+    return HELM_ENOMEM;
+  }
+  if (hipStreamBeginCapture(p->gcap, hipStreamCaptureModeRelaxed) != hipSuccess) return HELM_EDEVICE;
+  const int rc = enqueue_device_ir(p, F, U, nb, steps, p->opt.max_iter, static_cast<IrCtl*>(p->ctl_host), p->gcap);
+  hipGraph_t g = nullptr;
+  const hipError_t ce = hipStreamEndCapture(p->gcap, &g);
+  if (rc || ce != hipSuccess || !g) {
+    if (g) (void)hipGraphDestroy(g);
+    (void)hipGetLastError();
+    return rc ? rc : HELM_EDEVICE;
+  }
+  p->graph = g;
+  if (hipGraphInstantiate(&p->graph_exec, g, nullptr, nullptr, 0) != hipSuccess) {
+    p->drop_graph();
+    (void)hipGetLastError();
+    return HELM_EDEVICE;
+  }
+  p->graph_key = helm_plan::Key{F, U, nb, st};
+  p->graph_gen = p->ws_gen;
+  p->graph_steps = steps;
+  return HELM_OK;
+}
+
+// helm_solve.  The first call with given arguments runs eagerly with the
+// refinement loop on the host; a repeat of the same arguments (pointers,
+// count, stream) captures the solve with as many device-controlled
+// refinement steps as the previous call took and from then on launches the
+// graph.  When the captured steps do not reach the tolerance, the host loop
+// continues from the graph's last residual and the next call captures again
+// with the larger count.  Profiling (per-kernel events) always runs eagerly.
+int solve_entry(helm_plan* p, const void* f, void* u, int nrhs, hipStream_t st, bool allow_graph) {
+  if (!p || !f || !u || nrhs < 1) return HELM_EINVAL;
+  if (f == u) return HELM_EINVAL;
+  const bool mixed = p->opt.precision == HELM_PREC_MIXED;
+  const bool check = mixed || p->opt.check;
+  helm_report& rep = p->rep;
+  rep = helm_report{};
+  rep.precision = p->opt.precision;
+  rep.transform = p->dense ? HELM_TRANSFORM_DENSE : HELM_TRANSFORM_FFT;
+  rep.nrhs = nrhs;
+  rep.rel_residual_max = -1;
+  rep.rel_residual_first = -1;
+  int rc = ensure_workspace(p, nrhs, mixed, check);
+  if (rc) return rep.status = rc;
+  const double2* F = reinterpret_cast<const double2*>(f);
+  double2* U = reinterpret_cast<double2*>(u);
+  const int rk = mixed ? ST_C64 : ST_C128;
+  const helm_plan::Key key{f, u, nrhs, st};
+  const bool repeat = key == p->last_key;
+  const int prev = p->prev_steps;
+  p->last_key = key;
+  p->prev_steps = -1;  // set again when this call completes
+  int it = 0;
+  double rel = 0;
+  bool graph_ran = false;
+  if (allow_graph && !p->prof) {
+    if (p->graph_exec && !(p->graph_key == key && p->graph_gen == p->ws_gen)) p->drop_graph();
+    if (!p->graph_exec && repeat && prev >= 0) {
+      rc = capture_solve(p, F, U, nrhs, st, prev);
+      if (rc) return rep.status = rc;
+    }
+    if (p->graph_exec) {
+      if (hipGraphLaunch(p->graph_exec, st) != hipSuccess) return rep.status = HELM_EDEVICE;
+      if (!check) {
+        p->prev_steps = 0;
+        return rep.status = HELM_OK;
+      }
+      if (hipStreamSynchronize(st) != hipSuccess) return rep.status = HELM_EDEVICE;
+      IrCtl c;
+      std::memcpy(&c, p->ctl_host, sizeof(IrCtl));
+      graph_ran = true;
+      rep.rel_residual_first = (c.status == HELM_ENONFINITE && c.rel_first < 0) ? NAN : c.rel_first;
+      rep.rel_residual_max = c.rel_last;
+      if (c.done) {
+        rep.iterations = c.iters;
+        p->prev_steps = c.iters;
+        return rep.status = c.status;
+      }
+      // the captured steps were not enough: the host loop continues from the
+      // residual of the last captured step; the next call captures again
+      it = p->graph_steps;
+      rel = c.rel_last;
+      rep.iterations = it;
+      p->drop_graph();
+    }
+  }
+  if (!graph_ran) {
+    rc = solve_once(p, f, ST_C128, U, 0, nrhs, mixed, st);
+    if (rc) return rep.status = rc;
+    if (!check) {
+      p->prev_steps = 0;
+      return rep.status = HELM_OK;
+    }
+    rc = residual_norms(p, U, F, p->R.p, rk, nrhs, st, &rel, nullptr);
+    rep.rel_residual_first = rel;
+    rep.rel_residual_max = rel;
+    if (rc) return rep.status = rc;
+  }
+  while (rel > p->opt.tol && it < p->opt.max_iter) {
+    rc = solve_once(p, p->R.p, rk, U, 1, nrhs, mixed, st);
+    if (rc) return rep.status = rc;
+    ++it;
+    double nrel = 0;
+    rc = residual_norms(p, U, F, p->R.p, rk, nrhs, st, &nrel, nullptr);
+    rep.iterations = it;
+    rep.rel_residual_max = nrel;
+    if (rc) return rep.status = rc;
+    if (!(nrel < 0.5 * rel)) {
+      rel = nrel;
+      break;  // stagnation
+    }
+    rel = nrel;
+  }
+  p->prev_steps = it;
+  rep.status = rel <= p->opt.tol ? HELM_OK : HELM_ENOCONV;
+  return rep.status;
 }
 
 }  // namespace
@@ -1347,6 +1539,7 @@ struct helm_batch {
   std::vector<const void*> kf;
   std::vector<void*> ku;
   std::vector<int> kn;
+  std::vector<uint64_t> kgen;  // workspace generation of each plan at capture
   hipStream_t kst = nullptr;
   std::vector<int> steps;  // refinement steps captured per plan
   hipStream_t last = nullptr;
@@ -1546,49 +1739,7 @@ int helm_setup(int dim, const int64_t* grid, const double* h, double omega, uint
 }
 
 int helm_solve(helm_plan* p, const void* f, void* u, int nrhs, void* stream) {
-  if (!p || !f || !u || nrhs < 1) return HELM_EINVAL;
-  if (f == u) return HELM_EINVAL;
-  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-  const bool mixed = p->opt.precision == HELM_PREC_MIXED;
-  const bool check = mixed || p->opt.check;
-  helm_report& rep = p->rep;
-  rep = helm_report{};
-  rep.precision = p->opt.precision;
-  rep.transform = p->dense ? HELM_TRANSFORM_DENSE : HELM_TRANSFORM_FFT;
-  rep.nrhs = nrhs;
-  rep.rel_residual_max = -1;
-  rep.rel_residual_first = -1;
-  int rc = ensure_workspace(p, nrhs, mixed, check);
-  if (rc) return rep.status = rc;
-  const double2* F = reinterpret_cast<const double2*>(f);
-  double2* U = reinterpret_cast<double2*>(u);
-  rc = solve_once(p, f, ST_C128, U, 0, nrhs, mixed, st);
-  if (rc) return rep.status = rc;
-  if (!check) return rep.status = HELM_OK;
-  const int rk = mixed ? ST_C64 : ST_C128;
-  double rel = 0;
-  rc = residual_norms(p, U, F, p->R.p, rk, nrhs, st, &rel, nullptr);
-  rep.rel_residual_first = rel;
-  rep.rel_residual_max = rel;
-  if (rc) return rep.status = rc;
-  int it = 0;
-  while (rel > p->opt.tol && it < p->opt.max_iter) {
-    rc = solve_once(p, p->R.p, rk, U, 1, nrhs, mixed, st);
-    if (rc) return rep.status = rc;
-    ++it;
-    double nrel = 0;
-    rc = residual_norms(p, U, F, p->R.p, rk, nrhs, st, &nrel, nullptr);
-    rep.iterations = it;
-    rep.rel_residual_max = nrel;
-    if (rc) return rep.status = rc;
-    if (!(nrel < 0.5 * rel)) {
-      rel = nrel;
-      break;  // stagnation
-    }
-    rel = nrel;
-  }
-  rep.status = rel <= p->opt.tol ? HELM_OK : HELM_ENOCONV;
-  return rep.status;
+  return helm::solve_entry(p, f, u, nrhs, reinterpret_cast<hipStream_t>(stream), true);
 }
 
 int helm_report_get(const helm_plan* p, helm_report* out) {
@@ -1602,9 +1753,12 @@ int helm_residual(helm_plan* p, const void* u, const void* f, void* r, double* r
   if (!p || !u || !f || !rel_res || nrhs < 1) return HELM_EINVAL;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   const int64_t N = npoints(p);
-  if (p->scratch.ensure((size_t)residual_scratch_len(p->dim, p->grid, nrhs) * sizeof(double)) != hipSuccess)
-    return HELM_ENOMEM;
-  if (p->norms.ensure((size_t)nrhs * 2 * sizeof(double)) != hipSuccess) return HELM_ENOMEM;
+  const auto before = workspace_addrs(p);
+  const bool ok = p->scratch.ensure((size_t)residual_scratch_len(p->dim, p->grid, nrhs) * sizeof(double)) ==
+                      hipSuccess &&
+                  p->norms.ensure((size_t)nrhs * 2 * sizeof(double)) == hipSuccess;
+  if (workspace_addrs(p) != before) ++p->ws_gen;
+  if (!ok) return HELM_ENOMEM;
   p->h_norms.resize(2 * nrhs);
   (void)N;
   double mx = 0;
@@ -1688,7 +1842,8 @@ int helm_batch_solve(helm_batch* b, const void* const* f, void* const* u, const 
   }
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   bool same = b->exec && b->kst == st;
-  for (int i = 0; same && i < n; ++i) same = b->kf[i] == f[i] && b->ku[i] == u[i] && b->kn[i] == nrhs[i];
+  for (int i = 0; same && i < n; ++i)
+    same = b->kf[i] == f[i] && b->ku[i] == u[i] && b->kn[i] == nrhs[i] && b->kgen[i] == b->plans[i]->ws_gen;
   if (!same) {
     b->drop_graph();
     // Eager solves first: they create every lazily built table (twiddles,
@@ -1697,7 +1852,7 @@ int helm_batch_solve(helm_batch* b, const void* const* f, void* const* u, const 
     b->steps.assign(n, 0);
     for (int i = 0; i < n; ++i) {
       helm_plan* p = b->plans[i];
-      const int rc = helm_solve(p, f[i], u[i], nrhs[i], stream);
+      const int rc = helm::solve_entry(p, f[i], u[i], nrhs[i], st, false);
       if (rc != HELM_OK && rc != HELM_ENOCONV) return rc;
       b->steps[i] = std::min(p->opt.max_iter, std::max(2, p->rep.iterations + 1));
     }
@@ -1721,7 +1876,8 @@ int helm_batch_solve(helm_batch* b, const void* const* f, void* const* u, const 
         const int k = (int)(std::min_element(load.begin(), load.end()) - load.begin());
         load[k] += work(i);
         rc = enqueue_device_ir(b->plans[i], reinterpret_cast<const double2*>(f[i]),
-                               reinterpret_cast<double2*>(u[i]), nrhs[i], b->steps[i], b->side[k]);
+                               reinterpret_cast<double2*>(u[i]), nrhs[i], b->steps[i], b->steps[i], nullptr,
+                               b->side[k]);
         if (rc) break;
       }
       // join every side stream back (also after an error, so that the
@@ -1746,6 +1902,8 @@ int helm_batch_solve(helm_batch* b, const void* const* f, void* const* u, const 
     b->kf.assign(f, f + n);
     b->ku.assign(u, u + n);
     b->kn.assign(nrhs, nrhs + n);
+    b->kgen.resize(n);
+    for (int i = 0; i < n; ++i) b->kgen[i] = b->plans[i]->ws_gen;
     b->kst = st;
   }
   if (hipGraphLaunch(b->exec, st) != hipSuccess) return HELM_EDEVICE;

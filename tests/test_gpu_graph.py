@@ -1,0 +1,135 @@
+"""Repeated helm_solve calls on unchanged arguments run as a captured graph
+with device-controlled refinement.  The results must be those of the host
+loop (same kernels, same order: identical u), the report must agree, new data
+in the same buffers must be solved correctly, a graph whose captured steps
+fall short must hand over to the host loop, and workspace growth must drop
+every graph captured on the old buffers (single solve and batch).
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import fem
+from paper_1809_03808_amd import helm, inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def _abc(dim):
+    return tuple((True, True) for _ in range(dim))
+
+
+def _oracle_check(grid, omega, prec, f, u):
+    h = inputs.spacing(grid)
+    k = f.shape[0]
+    ref = fem.solve(grid, h, omega, _abc(len(grid)), f.reshape(k, -1))
+    err = np.max(fem.rel_error(u.reshape(k, -1), ref))
+    res = np.max(fem.rel_residual(grid, h, omega, _abc(len(grid)), u.reshape(k, -1), f.reshape(k, -1)))
+    if prec == helm.PREC_FP64:
+        assert err <= 1e-9, err
+    else:
+        assert res <= 1e-10 and err <= 1e-8, (res, err)
+    return err, res
+
+
+CASES = [  # grid, omega, precision, check, nrhs
+    ((257, 65), 80.0, helm.PREC_MIXED, True, 2),
+    ((64, 41), 30.0, helm.PREC_FP64, True, 1),
+    ((16, 16, 13), 14.0, helm.PREC_MIXED, True, 1),
+    ((96, 80), 40.0, helm.PREC_FP64, False, 1),
+]
+
+
+@pytest.mark.parametrize("case", range(len(CASES)))
+def test_repeated_solve_matches_first_call(case):
+    grid, omega, prec, check, k = CASES[case]
+    _say(f"graph repeat: grid {grid} omega {omega} prec {prec} check {check} nrhs {k}")
+    with helm.Plan(grid, inputs.spacing(grid), omega, precision=prec, check=check) as plan:
+        f_h = inputs.gaussian_batch(grid, [inputs.rhs_seed(9, case, r) for r in range(k)])
+        f = torch.from_numpy(f_h).cuda()
+        u = torch.empty_like(f)
+        plan.solve(f, u)
+        torch.cuda.synchronize()
+        u0 = u.cpu().numpy()
+        r0 = plan.report()
+        _oracle_check(grid, omega, prec, f_h, u0)
+        for rep in range(3):  # second call captures, later calls replay
+            u.fill_(0)
+            plan.solve(f, u)
+            torch.cuda.synchronize()
+            r = plan.report()
+            assert np.array_equal(u.cpu().numpy(), u0), f"call {rep + 2} differs from the first"
+            assert r["status"] == r0["status"] and r["iterations"] == r0["iterations"]
+            for key in ("rel_residual_first", "rel_residual_max"):
+                assert r[key] == pytest.approx(r0[key], rel=1e-12, abs=0.0)
+        # new data in the same buffers
+        f2_h = inputs.gaussian_batch(grid, [inputs.rhs_seed(9, case, 10 + r) for r in range(k)])
+        f.copy_(torch.from_numpy(f2_h))
+        plan.solve(f, u)
+        torch.cuda.synchronize()
+        assert plan.report()["status"] == helm.HELM_OK
+        err, res = _oracle_check(grid, omega, prec, f2_h, u.cpu().numpy())
+        _say(f"  replay with new data: err {err:.2e} res {res:.2e} report {plan.report()}")
+
+
+def test_short_graph_hands_over_to_host_loop():
+    grid, omega, prec = (257, 65), 80.0, helm.PREC_MIXED
+    with helm.Plan(grid, inputs.spacing(grid), omega, precision=prec) as plan:
+        f = torch.zeros((1,) + grid, dtype=torch.complex128, device="cuda")
+        u = torch.empty_like(f)
+        plan.solve(f, u)  # zero load: converged without refinement
+        torch.cuda.synchronize()
+        assert plan.report()["iterations"] == 0
+        assert not torch.any(u != 0)
+        f_h = inputs.gaussian_batch(grid, [inputs.rhs_seed(9, 7, 0)])
+        f.copy_(torch.from_numpy(f_h))
+        for call in range(3):  # captured with 0 steps, then recaptured with enough
+            u.fill_(0)
+            plan.solve(f, u)
+            torch.cuda.synchronize()
+            rep = plan.report()
+            _say(f"  call {call}: report {rep}")
+            assert rep["status"] == helm.HELM_OK and rep["iterations"] >= 1
+            assert rep["rel_residual_max"] <= 1e-10
+            _oracle_check(grid, omega, prec, f_h, u.cpu().numpy())
+
+
+def test_workspace_growth_drops_captured_graphs():
+    grid, omega, prec = (64, 41), 30.0, helm.PREC_MIXED
+    with helm.Plan(grid, inputs.spacing(grid), omega, precision=prec) as plan:
+        f_h = inputs.gaussian_batch(grid, [inputs.rhs_seed(9, 8, 0)])
+        f = torch.from_numpy(f_h).cuda()
+        u = torch.empty_like(f)
+        ub = torch.empty_like(f)
+        with helm.Batch([plan], max_nrhs=1) as batch:
+            for _ in range(2):
+                batch.solve([f], [ub])
+                plan.solve(f, u)
+                plan.solve(f, u)
+            torch.cuda.synchronize()
+            # three right-hand sides: the workspace grows and moves
+            f3_h = inputs.gaussian_batch(grid, [inputs.rhs_seed(9, 8, r) for r in range(1, 4)])
+            f3 = torch.from_numpy(f3_h).cuda()
+            u3 = torch.empty_like(f3)
+            plan.solve(f3, u3)
+            torch.cuda.synchronize()
+            _oracle_check(grid, omega, prec, f3_h, u3.cpu().numpy())
+            # the graphs captured before must not be launched on freed buffers
+            ub.fill_(0)
+            u.fill_(0)
+            batch.solve([f], [ub])
+            plan.solve(f, u)
+            plan.solve(f, u)
+            torch.cuda.synchronize()
+            assert batch.report(0)["status"] == helm.HELM_OK
+            assert plan.report()["status"] == helm.HELM_OK
+            _oracle_check(grid, omega, prec, f_h, ub.cpu().numpy())
+            _oracle_check(grid, omega, prec, f_h, u.cpu().numpy())
