@@ -33,15 +33,18 @@ __global__ __launch_bounds__(kMidThreads) void sum_partials_kernel(const double2
   out[i] = s;
 }
 
-// One block per (group, 30 columns): 8 tile slices x 32 columns (the 30
+// One block per (group, 30 columns): NT / 32 tile slices x 32 columns (the 30
 // outputs plus a halo of one on each side) sum the partials in parallel, the
 // slices are combined in LDS in a fixed order, then the 2x2 block operator is
-// applied.
+// applied.  With many partial tiles per group (few groups, long lines: the
+// 2D case) the partial sums are the bulk of the traffic and there are few
+// blocks, so blocks of 1024 threads keep more loads in flight.
 constexpr int kMidCols = 32;
-constexpr int kMidSlices = kMidThreads / kMidCols;
 constexpr int kMidOut = kMidCols - 2;
 
-__global__ __launch_bounds__(kMidThreads) void inner_mid_kernel(InnerMidArgs a) {
+template <int NT>
+__global__ __launch_bounds__(NT) void inner_mid_kernel(InnerMidArgs a) {
+  constexpr int kMidSlices = NT / kMidCols;
   __shared__ double2 sl[kMidSlices][2][kMidCols];
   __shared__ double2 v[2][kMidCols];
   if (a.skip && *a.skip) return;
@@ -56,6 +59,7 @@ __global__ __launch_bounds__(kMidThreads) void inner_mid_kernel(InnerMidArgs a) 
     double2 s0 = make_double2(0, 0), s1 = make_double2(0, 0);
     if (x >= 0 && x < nL) {
       const double2* p = a.part + g * a.ntiles * per + x;
+#pragma unroll 4
       for (int t = ts; t < a.ntiles; t += kMidSlices) {
         s0 = cadd(s0, p[t * per]);
         s1 = cadd(s1, p[t * per + nL]);
@@ -169,7 +173,10 @@ hipError_t launch_inner_mid(const InnerMidArgs& a, hipStream_t s) {
   const int ntx = (a.nL + kMidOut - 1) / kMidOut;
   const int64_t blocks = (int64_t)a.nb * a.nO * ntx;
   if (blocks <= 0) return hipSuccess;
-  hipLaunchKernelGGL(inner_mid_kernel, dim3((unsigned)blocks), dim3(kMidThreads), 0, s, a);
+  if (a.ntiles >= 64)
+    hipLaunchKernelGGL(inner_mid_kernel<1024>, dim3((unsigned)blocks), dim3(1024), 0, s, a);
+  else
+    hipLaunchKernelGGL(inner_mid_kernel<256>, dim3((unsigned)blocks), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

@@ -28,10 +28,20 @@ template <typename C> __device__ inline C cmul(C a, C b) {
   r.y = a.x * b.y + a.y * b.x;
   return r;
 }
-// a + b*c
+// a + b*c, as two fused multiply-adds per component (two roundings each)
 template <typename C> __device__ inline C cfma(C b, C c, C a) {
-  a.x += b.x * c.x - b.y * c.y;
-  a.y += b.x * c.y + b.y * c.x;
+  a.x = fma(b.x, c.x, a.x);
+  a.x = fma(-b.y, c.y, a.x);
+  a.y = fma(b.x, c.y, a.y);
+  a.y = fma(b.y, c.x, a.y);
+  return a;
+}
+// a - b*c, likewise
+template <typename C> __device__ inline C cfms(C b, C c, C a) {
+  a.x = fma(-b.x, c.x, a.x);
+  a.x = fma(b.y, c.y, a.x);
+  a.y = fma(-b.x, c.y, a.y);
+  a.y = fma(-b.y, c.x, a.y);
   return a;
 }
 template <typename C, typename S> __device__ inline C cscale(C a, S s) { a.x *= s; a.y *= s; return a; }

@@ -120,13 +120,28 @@ __device__ inline double dpp_d(double src, double old) {
                                                             ROWMASK, 0xF, false);
   return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
 }
+// Same with every row enabled and zero where no source lane exists
+// (bound_ctrl), which needs no initialised destination.
+template <int CTRL>
+__device__ inline double dpp_d0(double src) {
+  const unsigned long long s = __builtin_bit_cast(unsigned long long, src);
+  const unsigned lo = (unsigned)__builtin_amdgcn_mov_dpp((int)(unsigned)s, CTRL, 0xF, 0xF, true);
+  const unsigned hi = (unsigned)__builtin_amdgcn_mov_dpp((int)(unsigned)(s >> 32), CTRL, 0xF, 0xF, true);
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
 template <int CTRL, int ROWMASK = 0xF>
 __device__ inline Aff dpp_aff(const Aff& v) {  // identity where nothing arrives
   Aff o;
   o.f.x = dpp_d<CTRL, ROWMASK>(v.f.x, 1.0);
-  o.f.y = dpp_d<CTRL, ROWMASK>(v.f.y, 0.0);
-  o.g.x = dpp_d<CTRL, ROWMASK>(v.g.x, 0.0);
-  o.g.y = dpp_d<CTRL, ROWMASK>(v.g.y, 0.0);
+  if constexpr (ROWMASK == 0xF) {
+    o.f.y = dpp_d0<CTRL>(v.f.y);
+    o.g.x = dpp_d0<CTRL>(v.g.x);
+    o.g.y = dpp_d0<CTRL>(v.g.y);
+  } else {
+    o.f.y = dpp_d<CTRL, ROWMASK>(v.f.y, 0.0);
+    o.g.x = dpp_d<CTRL, ROWMASK>(v.g.x, 0.0);
+    o.g.y = dpp_d<CTRL, ROWMASK>(v.g.y, 0.0);
+  }
   return o;
 }
 // DPP controls (GFX9 encoding): row_shr:n = 0x110 + n, row_bcast:15 = 0x142,
@@ -493,11 +508,11 @@ __global__ __launch_bounds__(NT) void lines_kernel(LineDev a) {
           double2 pv;
           if (FIXED) {
             pv = (j == 0 && q == 0) ? rc.dlo : ((j == C - 1 && q == P - 1) ? rc.dhi : rc.dint);
-            pv = csub(pv, cmul(rc.off2, ipp));  // ipp = 0 at x = 0
+            pv = cfms(rc.off2, ipp, pv);  // ipp = 0 at x = 0
             ipp = crcp_fast(pv);
           } else {
             pv = diag_of(rc, x, nL);
-            if (has_e(x, nL)) pv = csub(pv, cmul(rc.off2, ipp));
+            if (has_e(x, nL)) pv = cfms(rc.off2, ipp, pv);
             ipp = x < nL ? crcp_fast(pv) : make_double2(1, 0);
           }
           S[slot_of(j)] = ipp;

@@ -1283,10 +1283,12 @@ int enqueue_device_ir(helm_plan* p, const double2* F, double2* U, int nb, int st
         rc = solve_once(p, p->R.p, rk, U, 1, nb, mixed, st);
         if (rc) break;
       }
+      // the residual itself is the right-hand side of the next step; after
+      // the last enqueued step only its norm is needed
       ResidArgs a = resid_args(p, nb);
       a.u = U;
       a.f = F;
-      a.r = p->R.p;
+      a.r = k < steps ? p->R.p : nullptr;
       a.r_kind = rk;
       if (launch_residual(a, st) != hipSuccess) { rc = HELM_EDEVICE; break; }
       hipLaunchKernelGGL(ir_check_kernel, dim3(1), dim3(1), 0, st, (const double*)a.norms, nb, p->opt.tol,
@@ -1386,12 +1388,15 @@ int solve_entry(helm_plan* p, const void* f, void* u, int nrhs, hipStream_t st, 
         p->prev_steps = c.iters;
         return rep.status = c.status;
       }
-      // the captured steps were not enough: the host loop continues from the
-      // residual of the last captured step; the next call captures again
+      // the captured steps were not enough: the host loop continues (the
+      // last captured residual kept only its norm, so it is formed again);
+      // the next call captures again
       it = p->graph_steps;
-      rel = c.rel_last;
       rep.iterations = it;
       p->drop_graph();
+      rc = residual_norms(p, U, F, p->R.p, rk, nrhs, st, &rel, nullptr);
+      rep.rel_residual_max = rel;
+      if (rc) return rep.status = rc;
     }
   }
   if (!graph_ran) {
