@@ -51,11 +51,12 @@ def _source_hash(paths):
     return h.hexdigest()[:16]
 
 
+_H = "paper_1809_03808_amd/csrc/helm_internal.h"
 KERNEL_SOURCES = {
-    "lines_kernel": ["paper_1809_03808_amd/csrc/lines.hip"],
-    "fft_pass_kernel<double2>": ["paper_1809_03808_amd/csrc/fft.hip"],
-    "fft_pass_kernel<float2>": ["paper_1809_03808_amd/csrc/fft.hip"],
-    "residual_kernel": ["paper_1809_03808_amd/csrc/stencil.hip"],
+    "lines_kernel": ["paper_1809_03808_amd/csrc/lines.hip", _H],
+    "fft_pass_kernel<double2>": ["paper_1809_03808_amd/csrc/fft.hip", _H],
+    "fft_pass_kernel<float2>": ["paper_1809_03808_amd/csrc/fft.hip", _H],
+    "residual_kernel": ["paper_1809_03808_amd/csrc/stencil.hip", _H],
 }
 
 
