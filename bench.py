@@ -119,7 +119,8 @@ def batch_leg(steps, warmup, count=64):
     1025, 2049}, 8-20 points per wavelength, 4 Gaussian right-hand sides
     each, complex64 storage + FP64 refinement to 1e-10) solved by one graph
     launch per step.  Also times the same problems solved one after another
-    with eager helm_solve calls on one stream."""
+    by separate helm_solve calls on one stream (each call synchronises; after
+    its first call each plan launches its own captured solve)."""
     import torch
     from paper_1809_03808_amd import helm, inputs
     import tempfile
@@ -155,12 +156,17 @@ def batch_leg(steps, warmup, count=64):
         chosen[key] = chosen.get(key, 0) + 1
     with open(tune) as fh:
         tune_lines = [ln.strip() for ln in fh if ln.strip()]
-    # eager reference: the same solves one after another on one stream
+    # reference: the same solves as separate helm_solve calls on one stream,
+    # timed once every plan has captured its own solve
+    for _ in range(2):
+        for p, f, u in zip(plans, fs, us):
+            p.solve(f, u)
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
     for p, f, u in zip(plans, fs, us):
         p.solve(f, u)
     torch.cuda.synchronize()
-    eager_ms = (time.perf_counter() - t0) * 1e3
+    seq_ms = (time.perf_counter() - t0) * 1e3
     batch.close()
     for p in plans:
         p.close()
@@ -175,7 +181,7 @@ def batch_leg(steps, warmup, count=64):
             "status_ok": all(r["status"] == 0 for r in reps),
             "rel_residual_max": max(r["rel_residual_max"] for r in reps),
             "refinement_steps_max": max(r["iterations"] for r in reps),
-            "eager_sequential_ms": round(eager_ms, 3), "graph_speedup_vs_eager": round(eager_ms / ms, 3),
+            "sequential_calls_ms": round(seq_ms, 3), "batch_speedup_vs_sequential_calls": round(seq_ms / ms, 3),
             "transform_chosen": chosen, "tuner_decisions": tune_lines,
             "setup_s": round(setup_s, 2), "first_call_s": round(first_s, 2)}
 
