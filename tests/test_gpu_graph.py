@@ -40,19 +40,21 @@ def _oracle_check(grid, omega, prec, f, u):
     return err, res
 
 
-CASES = [  # grid, omega, precision, check, nrhs
-    ((257, 65), 80.0, helm.PREC_MIXED, True, 2),
-    ((64, 41), 30.0, helm.PREC_FP64, True, 1),
-    ((16, 16, 13), 14.0, helm.PREC_MIXED, True, 1),
-    ((96, 80), 40.0, helm.PREC_FP64, False, 1),
+CASES = [  # grid, omega, precision, check, nrhs, transform
+    ((257, 65), 80.0, helm.PREC_MIXED, True, 2, helm.TRANSFORM_FFT),
+    ((64, 41), 30.0, helm.PREC_FP64, True, 1, helm.TRANSFORM_FFT),
+    ((16, 16, 13), 14.0, helm.PREC_MIXED, True, 1, helm.TRANSFORM_FFT),
+    ((96, 80), 40.0, helm.PREC_FP64, False, 1, helm.TRANSFORM_FFT),
+    ((64, 41), 30.0, helm.PREC_FP64, True, 2, helm.TRANSFORM_DENSE),
+    ((12, 10, 9), 8.0, helm.PREC_MIXED, True, 1, helm.TRANSFORM_DENSE),
 ]
 
 
 @pytest.mark.parametrize("case", range(len(CASES)))
 def test_repeated_solve_matches_first_call(case):
-    grid, omega, prec, check, k = CASES[case]
-    _say(f"graph repeat: grid {grid} omega {omega} prec {prec} check {check} nrhs {k}")
-    with helm.Plan(grid, inputs.spacing(grid), omega, precision=prec, check=check) as plan:
+    grid, omega, prec, check, k, tf = CASES[case]
+    _say(f"graph repeat: grid {grid} omega {omega} prec {prec} check {check} nrhs {k} transform {tf}")
+    with helm.Plan(grid, inputs.spacing(grid), omega, precision=prec, check=check, transform=tf) as plan:
         f_h = inputs.gaussian_batch(grid, [inputs.rhs_seed(9, case, r) for r in range(k)])
         f = torch.from_numpy(f_h).cuda()
         u = torch.empty_like(f)
