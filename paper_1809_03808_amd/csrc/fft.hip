@@ -132,6 +132,25 @@ template <typename C> __device__ inline void dft8(C* v, int sign) {
 template <> __device__ inline void dft<8, double2>(double2* v, int sign) { dft8(v, sign); }
 template <> __device__ inline void dft<8, float2>(float2* v, int sign) { dft8(v, sign); }
 
+// 3-point DFT with w = e^{sign 2 pi i / 3} = -1/2 + sign i sqrt(3)/2:
+// X0 = x0 + (x1 + x2), X1,2 = x0 - (x1 + x2)/2 +- sign i (sqrt(3)/2)(x1 - x2).
+template <typename C> __device__ inline void dft3(C* v, int sign) {
+  using T = typename RealOf<C>::T;
+  const T h = (T)0.86602540378443864676;  // sqrt(3)/2
+  const C t1 = cadd(v[1], v[2]), t2 = csub(v[1], v[2]);
+  C m;
+  m.x = v[0].x - (T)0.5 * t1.x;
+  m.y = v[0].y - (T)0.5 * t1.y;
+  C q = mul_si(t2, sign);
+  q.x *= h;
+  q.y *= h;
+  v[0] = cadd(v[0], t1);
+  v[1] = cadd(m, q);
+  v[2] = csub(m, q);
+}
+template <> __device__ inline void dft<3, double2>(double2* v, int sign) { dft3(v, sign); }
+template <> __device__ inline void dft<3, float2>(float2* v, int sign) { dft3(v, sign); }
+
 struct PassDev {
   int sign, acc, in_kind, out_kind;
   const void* cmode;
@@ -150,17 +169,26 @@ struct PassDev {
 
 // Compile-time Stockham plan of a power-of-two length L: one radix-2 or -4
 // stage first when log2(L) is not a multiple of 3, then radix-8 stages.
+// Lengths 9 * 2^k (the convolution pass of a chirp-z transform of length
+// 9 * 2^j) take the power-of-two stages of 2^k followed by two radix-3
+// stages.
 constexpr int ilog2(int L) { return L <= 1 ? 0 : 1 + ilog2(L / 2); }
-constexpr int nstages(int L) { return ilog2(L) / 3 + (ilog2(L) % 3 ? 1 : 0); }
+constexpr bool has9(int L) { return L % 9 == 0; }
+constexpr int p2part(int L) { return has9(L) ? L / 9 : L; }
+constexpr int nst2(int L2) { return ilog2(L2) / 3 + (ilog2(L2) % 3 ? 1 : 0); }
+constexpr int nstages(int L) { return nst2(p2part(L)) + (has9(L) ? 2 : 0); }
 constexpr int radix_of(int L, int s) {
-  return (ilog2(L) % 3 && s == 0) ? (ilog2(L) % 3 == 1 ? 2 : 4) : 8;
+  return s >= nst2(p2part(L)) ? 3
+                              : ((ilog2(p2part(L)) % 3 && s == 0) ? (ilog2(p2part(L)) % 3 == 1 ? 2 : 4) : 8);
 }
+constexpr int pow2_floor(int x) { return x < 2 ? 1 : 2 * pow2_floor(x / 2); }
 // Columns per tile: an LDS tile of L x W complex values, W <= kFftMaxW.
 // 32 KB tiles keep several blocks resident per compute unit; the longest
 // passes (L = 512) take 64 KB so that each row segment stays >= 128 bytes.
 constexpr int tile_bytes(int L) { return L >= 512 ? 2 * kFftLdsBytes : kFftLdsBytes; }
 template <typename C> constexpr int tile_w(int L) {
-  return (tile_bytes(L) / (L * (int)sizeof(C))) < kFftMaxW ? tile_bytes(L) / (L * (int)sizeof(C)) : kFftMaxW;
+  return pow2_floor((tile_bytes(L) / (L * (int)sizeof(C))) < kFftMaxW ? tile_bytes(L) / (L * (int)sizeof(C))
+                                                                       : kFftMaxW);
 }
 
 // One Stockham stage of radix R with Ns points already combined.  Thread
@@ -326,6 +354,10 @@ hipError_t launch_conv_L(const PassDev& p, int64_t O, const void* in, void* out,
 template <typename C>
 hipError_t launch_conv_typed(int L, const PassDev& p, int64_t O, const void* in, void* out, hipStream_t s) {
   switch (L) {
+    case 9: return launch_conv_L<9, C>(p, O, in, out, s);
+    case 18: return launch_conv_L<18, C>(p, O, in, out, s);
+    case 36: return launch_conv_L<36, C>(p, O, in, out, s);
+    case 72: return launch_conv_L<72, C>(p, O, in, out, s);
     case 2: return launch_conv_L<2, C>(p, O, in, out, s);
     case 4: return launch_conv_L<4, C>(p, O, in, out, s);
     case 8: return launch_conv_L<8, C>(p, O, in, out, s);

@@ -82,7 +82,8 @@ struct PAxis {
   BDiff bd;
   int na = 0, nbp = 0;  // FFT split n = na * nbp (nbp = first pass length); na = 1 -> one pass
   // Bluestein (chirp-z) transform for lengths that are not powers of two:
-  // convolution length M (power of two >= 2n - 1) split as Mna * Mnbp.
+  // convolution length M >= 2n - 1 (a power of two, or 9 * 2^j) split as
+  // Mna * Mnbp (Mna = 9 in the second case).
   int blue = 0, M = 0, Mna = 0, Mnbp = 0;
   DevMem btab;
   const void* chirp_d[2] = {nullptr, nullptr};  // w for sign -1, +1 (double2[n])
@@ -271,6 +272,43 @@ void host_fft(std::vector<cd>& x, int sign) {
   }
 }
 
+// DFT of any length of the form 2^j m with small odd m (here m = 1 or 9):
+// radix-2 decimation in time down to the odd length, which is summed
+// directly.  Host-side, for plan tables only.
+void host_dft(std::vector<cd>& x, int sign) {
+  const int n = (int)x.size();
+  if ((n & (n - 1)) == 0) {
+    host_fft(x, sign);
+    return;
+  }
+  if (n % 2) {
+    std::vector<cd> y(n);
+    for (int k = 0; k < n; ++k) {
+      cd acc(0.0);
+      for (int j = 0; j < n; ++j) {
+        const double th = sign * 2.0 * M_PI * (double)(((int64_t)j * k) % n) / n;
+        acc += x[j] * cd(std::cos(th), std::sin(th));
+      }
+      y[k] = acc;
+    }
+    x = y;
+    return;
+  }
+  std::vector<cd> e(n / 2), o(n / 2);
+  for (int j = 0; j < n / 2; ++j) {
+    e[j] = x[2 * j];
+    o[j] = x[2 * j + 1];
+  }
+  host_dft(e, sign);
+  host_dft(o, sign);
+  for (int k = 0; k < n / 2; ++k) {
+    const double th = sign * 2.0 * M_PI * k / n;
+    const cd t = o[k] * cd(std::cos(th), std::sin(th));
+    x[k] = e[k] + t;
+    x[k + n / 2] = e[k] - t;
+  }
+}
+
 void pow2_split(int L, int* na, int* nb) {
   if (L <= 512) {
     *na = 1;
@@ -286,14 +324,26 @@ void pow2_split(int L, int* na, int* nb) {
 // Bluestein tables of a periodised axis of length n (not a power of two):
 // chirp w_s[j] = e^{s pi i (j^2 mod 2n)/n} and the length-M forward DFT of the
 // kernel b_s[m] = e^{-s pi i m^2/n} (m in (-n, n), wrapped modulo M), s = -1, +1.
+// The convolution length M >= 2n - 1 is the smaller of the next power of two
+// and 9 * 2^j with 576 <= M <= 4608, split as 64 (the passes that carry the
+// chirps) times 9 * 2^(j - 6) (the convolution pass): for the paper's
+// n = 2^k + 1 that is 2.25 n instead of 4 n.
 int setup_bluestein(PAxis& a) {
   const int n = a.n;
   int M = 1;
   while (M < 2 * n - 1) M <<= 1;
   if (M > 512 * 512) return HELM_EUNSUPPORTED;
+  int M9 = 9;
+  while (M9 < 2 * n - 1) M9 <<= 1;
   a.blue = 1;
+  if (M9 < M && M9 >= 576 && M9 <= 4608) {
+    M = M9;
+    a.Mna = M9 / 64;
+    a.Mnbp = 64;
+  } else {
+    pow2_split(M, &a.Mna, &a.Mnbp);
+  }
   a.M = M;
-  pow2_split(M, &a.Mna, &a.Mnbp);
   std::vector<double2> hd((size_t)2 * n + 2 * M);
   std::vector<float2> hf((size_t)2 * n + 2 * M);
   for (int si = 0; si < 2; ++si) {
@@ -307,7 +357,7 @@ int setup_bluestein(PAxis& a) {
       b[j] = std::conj(w);
       if (j > 0) b[M - j] = std::conj(w);
     }
-    host_fft(b, -1);
+    host_dft(b, -1);
     for (int k = 0; k < M; ++k) hd[(size_t)2 * n + (size_t)si * M + k] = hd2(b[k]);
   }
   for (size_t i = 0; i < hd.size(); ++i) hf[i] = make_float2((float)hd[i].x, (float)hd[i].y);
@@ -347,13 +397,16 @@ Roots* get_roots(helm_plan* p, int L, int sign) {
 }
 
 void radix_plan(int L, FftPass& f) {
+  const bool m9 = L % 9 == 0;
+  const int L2 = m9 ? L / 9 : L;
   int p = 0;
-  while ((1 << p) < L) ++p;
+  while ((1 << p) < L2) ++p;
   f.nst = 0;
   const int rem = p % 3;
   if (rem == 1) f.radix[f.nst++] = 2;
   if (rem == 2) f.radix[f.nst++] = 4;
   for (int i = 0; i < p / 3; ++i) f.radix[f.nst++] = 8;
+  if (m9) f.radix[f.nst++] = 3, f.radix[f.nst++] = 3;
 }
 
 int pick_W(int L, int64_t, bool fp32) { return fft_tile_width(L, fp32); }
@@ -448,7 +501,8 @@ int run_pow2(helm_plan* p, int L, int na, int nb, int sign, bool fp32, const voi
 // Forward: sign -1 and per-mode scale 1/mu (if scale), inverse: sign +1, 1/n.
 // Lengths that are not powers of two use Bluestein's chirp-z algorithm:
 // jk = (j^2 + k^2 - (k - j)^2)/2 turns the DFT into a convolution with the
-// chirp kernel, evaluated with power-of-two transforms of length M >= 2n - 1.
+// chirp kernel, evaluated with transforms of length M >= 2n - 1 (a power of
+// two, or 9 * 2^j as a length-2^j pass and a length-9 convolution pass).
 // The chirp multiplications are folded into the first load and the last
 // store, and the convolution's middle (forward pass, kernel product, inverse
 // pass) is one kernel, so a transform costs n + M + 2M + M + n element moves

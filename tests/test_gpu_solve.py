@@ -59,7 +59,10 @@ CASES_2D = [
     ((12, 9), 6.0, 0b1111),
     ((257, 65), 80.0, 0b1111),
     ((100, 31), 30.0, 0b1100),
-    ((1025, 17), 300.0, 0b1111),  # chirp length 4096: two-pass inner transforms
+    ((1025, 17), 300.0, 0b1111),  # chirp length 2304 = 64 x 36: radix-4,3,3 convolution pass
+    ((513, 11), 150.0, 0b1111),   # chirp length 1152 = 64 x 18
+    ((2049, 9), 600.0, 0b1111),   # chirp length 4608 = 64 x 72
+    ((600, 13), 180.0, 0b1111),   # 2n - 1 = 1199: chirp length 2048 (smaller than 9 x 256)
     ((3, 7), 2.0, 0b1111),        # smallest periodised axis
 ]
 
@@ -101,6 +104,7 @@ CASES_3D = [
     ((12, 10, 9), 8.0, 0b111111),   # both periodised axes not powers of two
     ((8, 24, 7), 10.0, 0b111111),
     ((20, 16, 11), 12.0, 0b110111),
+    ((3, 257, 5), 40.0, 0b111111),  # x2 chirp length 576 = 64 x 9
 ]
 
 
