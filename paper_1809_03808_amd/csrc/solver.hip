@@ -325,9 +325,9 @@ void pow2_split(int L, int* na, int* nb) {
 // chirp w_s[j] = e^{s pi i (j^2 mod 2n)/n} and the length-M forward DFT of the
 // kernel b_s[m] = e^{-s pi i m^2/n} (m in (-n, n), wrapped modulo M), s = -1, +1.
 // The convolution length M >= 2n - 1 is the smaller of the next power of two
-// and 9 * 2^j with 576 <= M <= 4608, split as 64 (the passes that carry the
-// chirps) times 9 * 2^(j - 6) (the convolution pass): for the paper's
-// n = 2^k + 1 that is 2.25 n instead of 4 n.
+// and 9 * 2^j >= 576, split as nb (the passes that carry the chirps, a power
+// of two, 64 <= nb <= 512) times na = 9 * 2^k <= 72 (the convolution pass):
+// for the paper's n = 2^k + 1 that is 2.25 n instead of 4 n.
 int setup_bluestein(PAxis& a) {
   const int n = a.n;
   int M = 1;
@@ -336,10 +336,10 @@ int setup_bluestein(PAxis& a) {
   int M9 = 9;
   while (M9 < 2 * n - 1) M9 <<= 1;
   a.blue = 1;
-  if (M9 < M && M9 >= 576 && M9 <= 4608) {
+  if (M9 < M && M9 >= 576 && M9 <= 72 * 512) {
     M = M9;
-    a.Mna = M9 / 64;
-    a.Mnbp = 64;
+    a.Mnbp = M9 <= 4608 ? 64 : M9 / 72;
+    a.Mna = M9 / a.Mnbp;
   } else {
     pow2_split(M, &a.Mna, &a.Mnbp);
   }

@@ -62,6 +62,7 @@ CASES_2D = [
     ((1025, 17), 300.0, 0b1111),  # chirp length 2304 = 64 x 36: radix-4,3,3 convolution pass
     ((513, 11), 150.0, 0b1111),   # chirp length 1152 = 64 x 18
     ((2049, 9), 600.0, 0b1111),   # chirp length 4608 = 64 x 72
+    ((4097, 5), 1200.0, 0b1111),  # chirp length 9216 = 128 x 72
     ((600, 13), 180.0, 0b1111),   # 2n - 1 = 1199: chirp length 2048 (smaller than 9 x 256)
     ((3, 7), 2.0, 0b1111),        # smallest periodised axis
 ]
