@@ -351,7 +351,14 @@ __device__ inline int stage_pos(int e) { return e + (e >> 3); }
 // backward recurrence starts from y = 0, which annihilates its last backward
 // multiplier.  C = 0: chunk length a.c (<= kCMax) at run time, rows past the
 // end of the line are identity rows.
-template <typename T, int NT, int P, int C, bool RED>
+//
+// XR (with C = 8): the line has one row more, nL = P * 8 + 1 (the 2^k + 1
+// node counts of the paper's grids).  The last lane owns it beside its chunk:
+// it finishes the forward elimination through it after the forward scan
+// (its pivot and value follow from the chunk's last ones), takes y_{nL-1},
+// and folds it into its backward map, which becomes the constant map to the
+// value entering its chunk from above.
+template <typename T, int NT, int P, int C, bool RED, bool XR>
 __global__ __launch_bounds__(NT) void lines_kernel(LineDev a) {
   constexpr int NW = NT / 64;
   constexpr int PW = P < 64 ? P : 64;     // lanes of one line inside a wave
@@ -362,12 +369,13 @@ __global__ __launch_bounds__(NT) void lines_kernel(LineDev a) {
   extern __shared__ double2 stage[];      // NW areas of 72 c padded values
   if (a.skip && *a.skip) return;
 
-  const int c = FIXED ? C : a.c, nL = FIXED ? P * C : a.nL;
+  const int c = FIXED ? C : a.c, nL = FIXED ? P * C + (XR ? 1 : 0) : a.nL;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   // a line spans whole waves when P >= 64: its index is then wave-uniform
   const int slot = P >= 64 ? __builtin_amdgcn_readfirstlane(tid / P) : tid / P;
   const int q = tid - slot * P;
   const int x0 = q * c;
+  const bool last = XR && q == P - 1;  // owner of the extra row
   const int wslot0 = (wv * 64) / P;                   // first line slot of this wave
   const int wx0 = (P >= 64 ? (wv * 64) % P : 0) * c;  // first row this wave stages
   const int seg = PW * c;                             // rows of one line staged by this wave
@@ -385,6 +393,7 @@ __global__ __launch_bounds__(NT) void lines_kernel(LineDev a) {
   }
 
   double2 acc0[kCMax], acc1[kCMax];
+  double2 accx0 = make_double2(0, 0), accx1 = accx0;  // the extra row (XR, last lane)
   if constexpr (RED) {
 #pragma unroll
     for (int j = 0; j < kCMax; ++j) acc0[j] = acc1[j] = make_double2(0, 0);
@@ -393,7 +402,7 @@ __global__ __launch_bounds__(NT) void lines_kernel(LineDev a) {
   // Reducing launches with one line per block (P >= 256) prefetch the
   // next line's input rows into registers while the current line is solved,
   // so the load latency overlaps the sweeps.
-  constexpr bool PREF = P >= 256 && RED;
+  constexpr bool PREF = P >= 256 && RED && !XR;
   T pre[PREF ? kCMax : 1];
   auto fetch = [&](int itn) {
     uint32_t sb, sl, sm;
@@ -487,6 +496,22 @@ __global__ __launch_bounds__(NT) void lines_kernel(LineDev a) {
     double2 z[kCMax];
 #pragma unroll
     for (int j = 0; j < kCMax; ++j) z[j] = in_chunk(j) ? S[slot_of(j)] : make_double2(0, 0);
+    const int64_t loff = ((int64_t)(b * a.nO + l) * a.nI + m) * nL;  // this lane's line
+    double2 xrhs = make_double2(0, 0);  // right-hand side of the extra row
+    if (XR && last && valid) {
+      const int x = nL - 1;
+      if (a.in) xrhs = to_d2(reinterpret_cast<const T*>(a.in)[loff + x]);
+      if (a.PO) {
+        const double2* po = a.PO + (int64_t)(b * 2) * a.nI * nL + (int64_t)m * nL;
+        xrhs = cfma(a.alpha0[l], po[x], xrhs);
+        xrhs = cfma(a.alpha1[l], po[(int64_t)a.nI * nL + x], xrhs);
+      }
+      if (a.PI) {
+        const double2* pi = a.PI + (int64_t)((b * a.nO + l) * 2) * nL;
+        xrhs = cfma(a.beta0[m], pi[x], xrhs);
+        xrhs = cfma(a.beta1[m], pi[nL + x], xrhs);
+      }
+    }
 
     // ---- 1. pivots and forward composition --------------------------------
     // Reciprocal pivots: the chunk's entering value from the plan's factor
@@ -495,6 +520,7 @@ __global__ __launch_bounds__(NT) void lines_kernel(LineDev a) {
     // lane composes its rows into one affine map.
     const double2 ip_in = q > 0 ? a.piv[(int64_t)(l * a.nI + m) * P + q] : make_double2(0, 0);
     Aff A = aff_ident();
+    double2 ipp_last;  // 1/p of the chunk's last row
     {
       double2 ipp = ip_in;
 #pragma unroll
@@ -507,7 +533,7 @@ __global__ __launch_bounds__(NT) void lines_kernel(LineDev a) {
           A.g = cfma(f, A.g, z[j]);
           double2 pv;
           if (FIXED) {
-            pv = (j == 0 && q == 0) ? rc.dlo : ((j == C - 1 && q == P - 1) ? rc.dhi : rc.dint);
+            pv = (j == 0 && q == 0) ? rc.dlo : ((!XR && j == C - 1 && q == P - 1) ? rc.dhi : rc.dint);
             pv = cfms(rc.off2, ipp, pv);  // ipp = 0 at x = 0
             ipp = crcp_fast(pv);
           } else {
@@ -518,12 +544,14 @@ __global__ __launch_bounds__(NT) void lines_kernel(LineDev a) {
           S[slot_of(j)] = ipp;
         }
       }
+      ipp_last = ipp;
     }
     const Aff Ein = scan_fwd<P>(A, q, wbuf[0]);
 
     // ---- 2. forward values, scaled for the back substitution --------------
     // h_x = z_x / p_x; the lane's slots now take the backward multipliers
     // g_x = -e / p_x (zero where row x + 1 is past the end of the line).
+    double2 yx = make_double2(0, 0);  // y of the extra row (XR, last lane)
     {
       double2 zp = Ein.g;
       double2 mp = cmul(moff, ip_in);
@@ -539,6 +567,11 @@ __global__ __launch_bounds__(NT) void lines_kernel(LineDev a) {
           S[slot_of(j)] = (FIXED || has_e(x + 1, nL)) ? mp : make_double2(0, 0);
         }
       }
+      if (XR && last) {
+        // extra row: w = r + (-e / p_{nL-2}) w_{nL-2}, p = d_hi - e^2 / p_{nL-2}
+        const double2 wx = cfma(cmul(moff, ipp_last), zp, xrhs);
+        yx = cmul(wx, crcp_fast(cfms(rc.off2, ipp_last, rc.dhi)));
+      }
     }
 
     // ---- 3. back substitution y_x = g_x y_{x+1} + h_x: composition, scan ---
@@ -551,9 +584,13 @@ __global__ __launch_bounds__(NT) void lines_kernel(LineDev a) {
         B.g = cfma(gx, B.g, z[j]);
       }
     }
+    if (XR && last) {  // the value above the chunk is known: a constant map
+      B.g = cfma(B.f, yx, B.g);
+      B.f = make_double2(0, 0);
+    }
     const Aff Bin = scan_bwd<P>(B, q, wbuf[1]);
     {
-      double2 ynext = Bin.g;
+      double2 ynext = (XR && last) ? yx : Bin.g;
 #pragma unroll
       for (int j = kCMax - 1; j >= 0; --j) {
         if (in_chunk(j)) {
@@ -581,10 +618,15 @@ __global__ __launch_bounds__(NT) void lines_kernel(LineDev a) {
         }
       }
     }
+    if (XR && a.out && last && valid) reinterpret_cast<T*>(a.out)[loff + nL - 1] = from_d2<T>(yx);
     if constexpr (RED) {
       if (valid) {
         const uint32_t wi = (a.red == 1) ? m : l;
         const double2 w0 = a.rho0[wi], w1 = a.rho1[wi];
+        if (XR && last) {
+          accx0 = cfma(w0, yx, accx0);
+          accx1 = cfma(w1, yx, accx1);
+        }
 #pragma unroll
         for (int j = 0; j < kCMax; ++j) {
           if (in_chunk(j)) {
@@ -605,13 +647,16 @@ __global__ __launch_bounds__(NT) void lines_kernel(LineDev a) {
 #pragma unroll
       for (int j = 0; j < kCMax; ++j)
         if (in_chunk(j)) S[slot_of(j)] = k ? acc1[j] : acc0[j];
+      if constexpr (XR) S[lane * 9 + 8] = k ? accx1 : accx0;  // the lane's pad slot (c = 8)
       __syncthreads();
       for (int x = tid; x < nL; x += NT) {
-        const int qq = x / c, j = x - qq * c;
+        const bool xr = XR && x == nL - 1;
+        const int qq = xr ? P - 1 : x / c, j = x - qq * c;
         double2 s = make_double2(0, 0);
         for (int sl = 0; sl < LPB; ++sl) {
           const int owner = sl * P + qq;
-          s = cadd(s, stage[(owner >> 6) * (72 * c) + stage_pos((owner & 63) * c + j)]);
+          const int pos = xr ? (owner & 63) * 9 + 8 : stage_pos((owner & 63) * c + j);
+          s = cadd(s, stage[(owner >> 6) * (72 * c) + pos]);
         }
         outp[(int64_t)k * nL + x] = s;
       }
@@ -670,29 +715,36 @@ __global__ void factor_kernel(LineDev a, int P, double2* piv) {
   piv[line * P + q] = ip;
 }
 
-template <typename T, int NT, int P, int C, bool RED>
+template <typename T, int NT, int P, int C, bool RED, bool XR>
 hipError_t launch_R(const LineDev& d, int64_t blocks, hipStream_t s) {
   // staging areas: up to 72 KB at NT = 512, above the default dynamic LDS
   // limit, so raise the limit for this kernel once
   static bool attr = false;
   if (!attr) {
-    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&lines_kernel<T, NT, P, C, RED>),
+    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&lines_kernel<T, NT, P, C, RED, XR>),
                                              hipFuncAttributeMaxDynamicSharedMemorySize,
                                              (NT / 64) * 72 * kCMax * (int)sizeof(double2));
     if (e != hipSuccess) return e;
     attr = true;
   }
   const size_t lds = (size_t)(NT / 64) * 72 * d.c * sizeof(double2);
-  hipLaunchKernelGGL((lines_kernel<T, NT, P, C, RED>), dim3((unsigned)blocks), dim3(NT), lds, s, d);
+  hipLaunchKernelGGL((lines_kernel<T, NT, P, C, RED, XR>), dim3((unsigned)blocks), dim3(NT), lds, s, d);
   return hipGetLastError();
 }
 
 template <typename T, int NT, int P>
 hipError_t launch_P(const LineDev& d, int64_t blocks, hipStream_t s) {
   const bool fixed = d.c == kCMax && d.nL == P * kCMax;
+  const bool extra = d.c == kCMax && d.nL == P * kCMax + 1;
   if (fixed)
-    return d.red ? launch_R<T, NT, P, kCMax, true>(d, blocks, s) : launch_R<T, NT, P, kCMax, false>(d, blocks, s);
-  return d.red ? launch_R<T, NT, P, 0, true>(d, blocks, s) : launch_R<T, NT, P, 0, false>(d, blocks, s);
+    return d.red ? launch_R<T, NT, P, kCMax, true, false>(d, blocks, s)
+                 : launch_R<T, NT, P, kCMax, false, false>(d, blocks, s);
+  if constexpr (P >= 64) {
+    if (extra)
+      return d.red ? launch_R<T, NT, P, kCMax, true, true>(d, blocks, s)
+                   : launch_R<T, NT, P, kCMax, false, true>(d, blocks, s);
+  }
+  return d.red ? launch_R<T, NT, P, 0, true, false>(d, blocks, s) : launch_R<T, NT, P, 0, false, false>(d, blocks, s);
 }
 
 template <typename T>
@@ -737,11 +789,23 @@ LineDev make_dev(const LineArgs& a, int P, int c) {
 
 }  // namespace
 
+// Lines of P * 8 rows take P lanes of 8 rows; lines of P * 8 + 1 rows with
+// P >= 64 (the 2^k + 1 node counts from 513 up) the same lanes plus the
+// extra row of the last lane; other lengths the smallest power-of-two P with
+// P * 8 >= nL and ceil(nL / P) rows per lane.  (Below 64 lanes the extra-row
+// variant of the reducing kernel would drop to one wave per SIMD.)
 void lines_geometry(int nL, int* P, int* c, int* NT) {
   int p = 1;
-  while (p * kCMax < nL) p <<= 1;
-  *P = p;
-  *c = (nL + p - 1) / p;
+  if (nL > 8 && (nL - 1) % kCMax == 0 && (((nL - 1) / kCMax) & ((nL - 1) / kCMax - 1)) == 0 &&
+      (nL - 1) / kCMax >= 64 && (nL - 1) / kCMax <= 512) {
+    p = (nL - 1) / kCMax;
+    *P = p;
+    *c = kCMax;
+  } else {
+    while (p * kCMax < nL) p <<= 1;
+    *P = p;
+    *c = (nL + p - 1) / p;
+  }
   *NT = p > 256 ? p : 256;
 }
 

@@ -1676,10 +1676,10 @@ int helm_setup(int dim, const int64_t* grid, const double* h, double omega, uint
     p->h[j] = h[j];
   }
   // size limits of this build, checked before any device call: line axis
-  // <= 4096 nodes (at most 512 lanes of 8 rows), periodised lengths whose
-  // transform splits into two passes of <= 512 (power of two <= 2^18, or a
-  // chirp-z convolution length <= 2^18)
-  if (grid[last] > 4096) return HELM_EUNSUPPORTED;
+  // <= 4096 nodes (at most 512 lanes of 8 rows) or 4097 (512 lanes and the
+  // extra row), periodised lengths whose transform splits into two passes of
+  // <= 512 (power of two <= 2^18, or a chirp-z convolution length <= 2^18)
+  if (grid[last] > 4097) return HELM_EUNSUPPORTED;
   for (int j = 0; j < dim - 1; ++j) {
     int64_t M = 1;
     while (M < (is_pow2(grid[j]) ? grid[j] : 2 * grid[j] - 1)) M <<= 1;
@@ -1691,7 +1691,7 @@ int helm_setup(int dim, const int64_t* grid, const double* h, double omega, uint
   p->hL = h[last];
   p->kLo = make_double2(1.0, ((abc >> (2 * last)) & 1) ? -omega * h[last] : 0.0);
   p->kHi = make_double2(1.0, ((abc >> (2 * last + 1)) & 1) ? -omega * h[last] : 0.0);
-  if (p->nL > 4096) return HELM_EUNSUPPORTED;
+  if (p->nL > 4097) return HELM_EUNSUPPORTED;
   for (int j = 0; j < p->nper; ++j) {
     PAxis& a = p->ax[j];
     a.n = (int)grid[j];

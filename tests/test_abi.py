@@ -84,10 +84,10 @@ def test_dense_transform_size_limit():
     assert e.value.code == helm.HELM_EINVAL
 
 
-@pytest.mark.parametrize("grid", [(16, 4097), (131073, 16), (262145, 16), (16, 140000, 9)])
+@pytest.mark.parametrize("grid", [(16, 4098), (16, 8193), (131073, 16), (262145, 16), (16, 140000, 9)])
 def test_setup_size_limits(grid):
     """Lengths beyond this build's limits are refused before any device call:
-    a line axis above 4096 nodes, a periodised length whose transform would
+    a line axis above 4097 nodes, a periodised length whose transform would
     need more than two passes of 512."""
     h = tuple(1.0 / (n - 1) for n in grid)
     with pytest.raises(helm.HelmError) as e:

@@ -65,6 +65,10 @@ CASES_2D = [
     ((4097, 5), 1200.0, 0b1111),  # chirp length 9216 = 128 x 72
     ((600, 13), 180.0, 0b1111),   # 2n - 1 = 1199: chirp length 2048 (smaller than 9 x 256)
     ((3, 7), 2.0, 0b1111),        # smallest periodised axis
+    # line lengths 8 P + 1 (P = 64, 128, 256 lanes plus the extra row)
+    ((4, 513), 150.0, 0b1111),
+    ((4, 1025), 300.0, 0b1111),
+    ((3, 2049), 600.0, 0b0111),   # x2 high face Neumann
 ]
 
 
@@ -106,6 +110,7 @@ CASES_3D = [
     ((8, 24, 7), 10.0, 0b111111),
     ((20, 16, 11), 12.0, 0b110111),
     ((3, 257, 5), 40.0, 0b111111),  # x2 chirp length 576 = 64 x 9
+    ((3, 3, 513), 150.0, 0b111111),  # lines of 8 x 64 + 1 rows
 ]
 
 
@@ -121,7 +126,8 @@ def test_3d_fp64_matches_banded_lu(grid, omega, mask):
 
 
 @pytest.mark.parametrize("grid,omega", [((64, 77), 35.0), ((16, 16, 13), 14.0), ((1024, 17), 300.0),
-                                         ((513, 33), 150.0), ((12, 20, 9), 12.0)])
+                                         ((513, 33), 150.0), ((12, 20, 9), 12.0), ((16, 1025), 300.0),
+                                         ((3, 4097), 1200.0)])
 def test_mixed_precision_refines_to_1e10(grid, omega):
     mask = (1 << (2 * len(grid))) - 1
     f = inputs.gaussian_batch(grid, [31, 32, 33]).astype(np.complex128)
