@@ -100,9 +100,12 @@ typedef struct helm_plan helm_plan;
  * (eqs. (eigvectorsPer), (eigvaluesPer)) and the absorbing-boundary
  * generalized eigenpairs K V = M V Lambda^A (eq. (EVP1a), normalised as in
  * eq. (EVPcondA)), then uploads them to the current HIP device.
+ * Size limits of this build: the last (line) axis has at most 4097 nodes;
+ * a periodised axis of n nodes needs a transform length (n itself for a power
+ * of two, else a chirp-z length >= 2n - 1) of at most 2^18.
  * Errors: HELM_EINVAL, HELM_ESINGULAR (omega = 0 and no absorbing face),
  * HELM_EUNSUPPORTED (a periodised axis with mixed face conditions, or a
- * periodised length this build cannot transform), HELM_ENOMEM, HELM_EDEVICE.
+ * length beyond the limits above), HELM_ENOMEM, HELM_EDEVICE.
  */
 int helm_setup(int dim, const int64_t* grid, const double* h, double omega,
                uint32_t abc, const helm_options* opt, helm_plan** out);
