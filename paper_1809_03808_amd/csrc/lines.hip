@@ -349,8 +349,9 @@ __device__ inline int stage_pos(int e) { return e + (e >> 3); }
 // x = nL - 1, and neither needs a guard: the entering reciprocal pivot of lane
 // 0 is zero, which zeroes its first forward multiplier, and the last lane's
 // backward recurrence starts from y = 0, which annihilates its last backward
-// multiplier.  C = 0: chunk length a.c (<= kCMax) at run time, rows past the
-// end of the line are identity rows.
+// multiplier.  PAD (C = 8, nL < P * 8 at run time): the rows past the end of
+// the line are identity rows, with the couplings and end pivot guarded per
+// row.  C = 0: chunk length a.c (<= kCMax) at run time, likewise guarded.
 //
 // XR (with C = 8): the line has one row more, nL = P * 8 + 1 (the 2^k + 1
 // node counts of the paper's grids).  The last lane owns it beside its chunk:
@@ -358,18 +359,19 @@ __device__ inline int stage_pos(int e) { return e + (e >> 3); }
 // (its pivot and value follow from the chunk's last ones), takes y_{nL-1},
 // and folds it into its backward map, which becomes the constant map to the
 // value entering its chunk from above.
-template <typename T, int NT, int P, int C, bool RED, bool XR>
+template <typename T, int NT, int P, int C, bool RED, bool XR, bool PAD>
 __global__ __launch_bounds__(NT) void lines_kernel(LineDev a) {
   constexpr int NW = NT / 64;
   constexpr int PW = P < 64 ? P : 64;     // lanes of one line inside a wave
   constexpr int SPW = 64 / PW;            // lines per wave
   constexpr int LPB = NT / P;             // lines per block
   constexpr bool FIXED = C > 0;
+  constexpr bool EXACT = FIXED && !PAD;  // every row of every chunk is a row of the line
   __shared__ Aff wbuf[2][NW + 1];         // wave totals of the forward / backward scans
   extern __shared__ double2 stage[];      // NW areas of 72 c padded values
   if (a.skip && *a.skip) return;
 
-  const int c = FIXED ? C : a.c, nL = FIXED ? P * C + (XR ? 1 : 0) : a.nL;
+  const int c = FIXED ? C : a.c, nL = EXACT ? P * C + (XR ? 1 : 0) : a.nL;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   // a line spans whole waves when P >= 64: its index is then wave-uniform
   const int slot = P >= 64 ? __builtin_amdgcn_readfirstlane(tid / P) : tid / P;
@@ -528,11 +530,11 @@ __global__ __launch_bounds__(NT) void lines_kernel(LineDev a) {
         if (in_chunk(j)) {
           const int x = x0 + j;
           double2 f = cmul(moff, ipp);
-          if (!FIXED && !has_e(x, nL)) f = make_double2(0, 0);
+          if (!EXACT && !has_e(x, nL)) f = make_double2(0, 0);
           A.f = cmul(f, A.f);
           A.g = cfma(f, A.g, z[j]);
           double2 pv;
-          if (FIXED) {
+          if (EXACT) {
             pv = (j == 0 && q == 0) ? rc.dlo : ((!XR && j == C - 1 && q == P - 1) ? rc.dhi : rc.dint);
             pv = cfms(rc.off2, ipp, pv);  // ipp = 0 at x = 0
             ipp = crcp_fast(pv);
@@ -559,12 +561,12 @@ __global__ __launch_bounds__(NT) void lines_kernel(LineDev a) {
       for (int j = 0; j < kCMax; ++j) {
         if (in_chunk(j)) {
           const int x = x0 + j;
-          const double2 f = (FIXED || has_e(x, nL)) ? mp : make_double2(0, 0);
+          const double2 f = (EXACT || has_e(x, nL)) ? mp : make_double2(0, 0);
           zp = cfma(f, zp, z[j]);
           const double2 ipj = S[slot_of(j)];
           z[j] = cmul(zp, ipj);
           mp = cmul(moff, ipj);
-          S[slot_of(j)] = (FIXED || has_e(x + 1, nL)) ? mp : make_double2(0, 0);
+          S[slot_of(j)] = (EXACT || has_e(x + 1, nL)) ? mp : make_double2(0, 0);
         }
       }
       if (XR && last) {
@@ -715,36 +717,40 @@ __global__ void factor_kernel(LineDev a, int P, double2* piv) {
   piv[line * P + q] = ip;
 }
 
-template <typename T, int NT, int P, int C, bool RED, bool XR>
+template <typename T, int NT, int P, int C, bool RED, bool XR, bool PAD>
 hipError_t launch_R(const LineDev& d, int64_t blocks, hipStream_t s) {
   // staging areas: up to 72 KB at NT = 512, above the default dynamic LDS
   // limit, so raise the limit for this kernel once
   static bool attr = false;
   if (!attr) {
-    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&lines_kernel<T, NT, P, C, RED, XR>),
+    const hipError_t e =
+        hipFuncSetAttribute(reinterpret_cast<const void*>(&lines_kernel<T, NT, P, C, RED, XR, PAD>),
                                              hipFuncAttributeMaxDynamicSharedMemorySize,
                                              (NT / 64) * 72 * kCMax * (int)sizeof(double2));
     if (e != hipSuccess) return e;
     attr = true;
   }
   const size_t lds = (size_t)(NT / 64) * 72 * d.c * sizeof(double2);
-  hipLaunchKernelGGL((lines_kernel<T, NT, P, C, RED, XR>), dim3((unsigned)blocks), dim3(NT), lds, s, d);
+  hipLaunchKernelGGL((lines_kernel<T, NT, P, C, RED, XR, PAD>), dim3((unsigned)blocks), dim3(NT), lds, s, d);
   return hipGetLastError();
 }
 
+// Every geometry has 8-row chunks (lines_geometry): exact lines, lines with
+// the extra row, or lines shorter than P * 8 (padded).
 template <typename T, int NT, int P>
 hipError_t launch_P(const LineDev& d, int64_t blocks, hipStream_t s) {
-  const bool fixed = d.c == kCMax && d.nL == P * kCMax;
-  const bool extra = d.c == kCMax && d.nL == P * kCMax + 1;
-  if (fixed)
-    return d.red ? launch_R<T, NT, P, kCMax, true, false>(d, blocks, s)
-                 : launch_R<T, NT, P, kCMax, false, false>(d, blocks, s);
+  if (d.c != kCMax) return hipErrorInvalidValue;
+  if (d.nL == P * kCMax)
+    return d.red ? launch_R<T, NT, P, kCMax, true, false, false>(d, blocks, s)
+                 : launch_R<T, NT, P, kCMax, false, false, false>(d, blocks, s);
   if constexpr (P >= 64) {
-    if (extra)
-      return d.red ? launch_R<T, NT, P, kCMax, true, true>(d, blocks, s)
-                   : launch_R<T, NT, P, kCMax, false, true>(d, blocks, s);
+    if (d.nL == P * kCMax + 1)
+      return d.red ? launch_R<T, NT, P, kCMax, true, true, false>(d, blocks, s)
+                   : launch_R<T, NT, P, kCMax, false, true, false>(d, blocks, s);
   }
-  return d.red ? launch_R<T, NT, P, 0, true, false>(d, blocks, s) : launch_R<T, NT, P, 0, false, false>(d, blocks, s);
+  if (d.nL > P * kCMax) return hipErrorInvalidValue;
+  return d.red ? launch_R<T, NT, P, kCMax, true, false, true>(d, blocks, s)
+               : launch_R<T, NT, P, kCMax, false, false, true>(d, blocks, s);
 }
 
 template <typename T>
@@ -792,8 +798,9 @@ LineDev make_dev(const LineArgs& a, int P, int c) {
 // Lines of P * 8 rows take P lanes of 8 rows; lines of P * 8 + 1 rows with
 // P >= 64 (the 2^k + 1 node counts from 513 up) the same lanes plus the
 // extra row of the last lane; other lengths the smallest power-of-two P with
-// P * 8 >= nL and ceil(nL / P) rows per lane.  (Below 64 lanes the extra-row
-// variant of the reducing kernel would drop to one wave per SIMD.)
+// P * 8 >= nL, the rows past the end being identity rows.  (Below 64 lanes
+// the extra-row variant of the reducing kernel would drop to one wave per
+// SIMD.)
 void lines_geometry(int nL, int* P, int* c, int* NT) {
   int p = 1;
   if (nL > 8 && (nL - 1) % kCMax == 0 && (((nL - 1) / kCMax) & ((nL - 1) / kCMax - 1)) == 0 &&
@@ -804,7 +811,7 @@ void lines_geometry(int nL, int* P, int* c, int* NT) {
   } else {
     while (p * kCMax < nL) p <<= 1;
     *P = p;
-    *c = (nL + p - 1) / p;
+    *c = kCMax;
   }
   *NT = p > 256 ? p : 256;
 }
