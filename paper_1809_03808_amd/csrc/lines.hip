@@ -351,7 +351,9 @@ __device__ inline int stage_pos(int e) { return e + (e >> 3); }
 // backward recurrence starts from y = 0, which annihilates its last backward
 // multiplier.  PAD (C = 8, nL < P * 8 at run time): the rows past the end of
 // the line are identity rows, with the couplings and end pivot guarded per
-// row.  C = 0: chunk length a.c (<= kCMax) at run time, likewise guarded.
+// row.  (C = 0, a chunk length a.c <= kCMax read at run time with the same
+// guards, is the general form; the launcher always picks 8-row chunks,
+// which run about a third faster.)
 //
 // XR (with C = 8): the line has one row more, nL = P * 8 + 1 (the 2^k + 1
 // node counts of the paper's grids).  The last lane owns it beside its chunk:
