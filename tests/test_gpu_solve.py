@@ -54,6 +54,7 @@ CASES_2D = [
     ((32, 33), 20.0, 0b1100),   # x1 both Neumann
     ((64, 41), 30.0, 0b0110),   # mixed faces on both axes
     ((1024, 21), 400.0, 0b1111),  # two-pass transform along x1
+    ((512, 9), 150.0, 0b1111),    # one 512-point pass (128 KB tile, 1024 threads)
     # periodised lengths that are not powers of two (chirp-z transform)
     ((33, 20), 15.0, 0b1111),
     ((12, 9), 6.0, 0b1111),
@@ -110,6 +111,7 @@ CASES_3D = [
     ((8, 24, 7), 10.0, 0b111111),
     ((20, 16, 11), 12.0, 0b110111),
     ((3, 257, 5), 40.0, 0b111111),  # x2 chirp length 576 = 64 x 9
+    ((3, 512, 5), 150.0, 0b111111),  # one 512-point pass along x2
     ((3, 3, 513), 150.0, 0b111111),  # lines of 8 x 64 + 1 rows
 ]
 
@@ -127,7 +129,7 @@ def test_3d_fp64_matches_banded_lu(grid, omega, mask):
 
 @pytest.mark.parametrize("grid,omega", [((64, 77), 35.0), ((16, 16, 13), 14.0), ((1024, 17), 300.0),
                                          ((513, 33), 150.0), ((12, 20, 9), 12.0), ((16, 1025), 300.0),
-                                         ((3, 4097), 1200.0)])
+                                         ((3, 4097), 1200.0), ((512, 17), 150.0)])
 def test_mixed_precision_refines_to_1e10(grid, omega):
     mask = (1 << (2 * len(grid))) - 1
     f = inputs.gaussian_batch(grid, [31, 32, 33]).astype(np.complex128)
