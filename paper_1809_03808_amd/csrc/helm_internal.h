@@ -140,6 +140,8 @@ hipError_t launch_fft_pass(const FftPass& p, bool fp32, const void* in, void* ou
 // Output: store the solution to out[b][l][m][:] and/or reduce
 //   red == 1: part[((b nO + l) ntiles + t)][k][:] = sum_{m in tile t} rho_k[m] y
 //   red == 2: part[((b nI + m) ntiles + t)][k][:] = sum_{l in tile t} rho_k[l] y
+//   red == 3: the sums of red == 2 with the lines of a block taken as
+//             consecutive m at one l per iteration (all l in one tile)
 // ---------------------------------------------------------------------------
 struct LineArgs {
   int nb = 1, nO = 1, nI = 1, nL = 0;

@@ -301,10 +301,15 @@ __device__ inline bool has_e(int x, int nL) { return x > 0 && x < nL; }
 
 // Line index (b, l, m) of slot `sl` of tile t at iteration `it`; false past
 // the end of the tile's extent.  Line counts stay below 2^31 (checked at
-// launch), so 32-bit index arithmetic suffices.
+// launch), so 32-bit index arithmetic suffices.  Reductions over l come in
+// two layouts: red 2 gives a block one m and its slots consecutive l (lines
+// nI nL elements apart); red 3 gives the slots of a block lpb consecutive m
+// at one l per iteration, so one iteration reads lpb adjacent lines and the
+// rows PI[b][l] once, and every slot keeps its own partial sum.
 __device__ inline bool decode_line(const LineDev& a, uint32_t g, uint32_t t, int lpb, int it, int sl,
                                    uint32_t& b, uint32_t& l, uint32_t& m) {
-  const uint32_t li = t * (uint32_t)a.tile + (uint32_t)(it * lpb + sl);
+  const uint32_t li = a.red == 3 ? t * (uint32_t)a.tile + (uint32_t)it
+                                 : t * (uint32_t)a.tile + (uint32_t)(it * lpb + sl);
   const uint32_t nO = a.nO, nI = a.nI;
   bool valid;
   if (a.red == 1) {        // g = b*nO + l, li = m
@@ -317,6 +322,12 @@ __device__ inline bool decode_line(const LineDev& a, uint32_t g, uint32_t t, int
     b = g / nI;
     m = g - b * nI;
     l = li;
+  } else if (a.red == 3) { // g = b*nmg + mg, li = l, m = mg*lpb + sl
+    const uint32_t nmg = (nI + (uint32_t)lpb - 1) / (uint32_t)lpb;
+    b = g / nmg;
+    m = (g - b * nmg) * (uint32_t)lpb + (uint32_t)sl;
+    l = li;
+    valid = li < nO && m < nI;
   } else {                 // li = (b*nO + l)*nI + m
     valid = li < (uint32_t)a.nb * nO * nI;
     const uint32_t bl = li / nI;
@@ -653,6 +664,22 @@ __global__ __launch_bounds__(NT) void lines_kernel(LineDev a) {
         if (in_chunk(j)) S[slot_of(j)] = k ? acc1[j] : acc0[j];
       if constexpr (XR) S[lane * 9 + 8] = k ? accx1 : accx0;  // the lane's pad slot (c = 8)
       __syncthreads();
+      if (a.red == 3) {
+        // one partial per slot: part[(b nI + m) ntiles + t][k][x], m = mg LPB + sl
+        const uint32_t nmg = ((uint32_t)a.nI + LPB - 1) / LPB;
+        const uint32_t b3 = g / nmg, m0 = (g - b3 * nmg) * LPB;
+        for (int e = tid; e < LPB * nL; e += NT) {
+          const int sl = e / nL, x = e - sl * nL;
+          if (m0 + (uint32_t)sl >= (uint32_t)a.nI) continue;
+          const bool xr = XR && x == nL - 1;
+          const int qq = xr ? P - 1 : x / c, j = x - qq * c;
+          const int owner = sl * P + qq;
+          const int pos = xr ? (owner & 63) * 9 + 8 : stage_pos((owner & 63) * c + j);
+          a.part[(((int64_t)b3 * a.nI + m0 + sl) * a.ntiles + t) * 2 * nL + (int64_t)k * nL + x] =
+              stage[(owner >> 6) * (72 * c) + pos];
+        }
+        continue;
+      }
       for (int x = tid; x < nL; x += NT) {
         const bool xr = XR && x == nL - 1;
         const int qq = xr ? P - 1 : x / c, j = x - qq * c;
@@ -838,9 +865,11 @@ hipError_t launch_lines(LineArgs a, hipStream_t s) {
   LineDev d = make_dev(a, P, c);
   const int LPB = NT / P;
   int64_t blocks;
-  if (a.red == 1 || a.red == 2) {
+  if (a.red == 1 || a.red == 2 || a.red == 3) {
     const int64_t extent = a.red == 1 ? a.nI : a.nO;
-    const int64_t groups = a.red == 1 ? (int64_t)a.nb * a.nO : (int64_t)a.nb * a.nI;
+    const int64_t groups = a.red == 1   ? (int64_t)a.nb * a.nO
+                           : a.red == 2 ? (int64_t)a.nb * a.nI
+                                        : (int64_t)a.nb * ((a.nI + LPB - 1) / LPB);
     d.tile = a.tile;
     d.ntiles = (int)((extent + a.tile - 1) / a.tile);
     if (d.ntiles != a.ntiles) return hipErrorInvalidValue;
@@ -851,8 +880,12 @@ hipError_t launch_lines(LineArgs a, hipStream_t s) {
     d.ntiles = (int)((lines + a.tile - 1) / a.tile);
     blocks = d.ntiles;
   }
-  if (d.tile % LPB) return hipErrorInvalidValue;
-  d.iters = d.tile / LPB;
+  if (a.red == 3) {
+    d.iters = d.tile;  // one l per iteration, the slots take LPB consecutive m
+  } else {
+    if (d.tile % LPB) return hipErrorInvalidValue;
+    d.iters = d.tile / LPB;
+  }
   if (blocks <= 0) return hipSuccess;
   if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
   // one storage kind for the input and output lines

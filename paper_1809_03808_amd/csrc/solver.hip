@@ -20,6 +20,7 @@
 #include <memory>
 #include <string>
 #include <cstdio>
+#include <cstdlib>
 
 #include "helm_internal.h"
 
@@ -661,10 +662,29 @@ int run_fft(helm_plan* p, const PAxis& a, int sign, bool fp32, const void* in, i
 // at once (one 512-thread or two 256-thread blocks per compute unit at the
 // register use of the reducing kernels) and no more; other launches take up
 // to 2048 blocks.
+// Layout of a reduction over l (red 2 or 3, see the line kernel): with at
+// least 1024 groups of LPB consecutive m (b < nb), every block takes LPB
+// adjacent lines per iteration (red 3, all l in one tile); otherwise one m per
+// block with its slots over l (red 2).  HELM_RED_L_LAYOUT=2 or 3 in the
+// environment selects one of them for every size (both compute the same sums).
+int red_l_mode(int nb, int nI, int nL) {
+  const char* env = std::getenv("HELM_RED_L_LAYOUT");
+  if (env && (env[0] == '2' || env[0] == '3') && env[1] == 0) return env[0] - '0';
+  int P, c, NT;
+  lines_geometry(nL, &P, &c, &NT);
+  const int LPB = NT / P;
+  return LPB > 1 && (int64_t)nb * ((nI + LPB - 1) / LPB) >= 1024 ? 3 : 2;
+}
+
 void tiles_for(int red, int nb, int nO, int nI, int nL, int* tile, int* ntiles) {
   int P, c, NT;
   lines_geometry(nL, &P, &c, &NT);
   const int LPB = NT / P;
+  if (red == 2 && red_l_mode(nb, nI, nL) == 3) {
+    *tile = nO;
+    *ntiles = 1;
+    return;
+  }
   const int64_t extent = red == 1 ? nI : (red == 2 ? nO : (int64_t)nb * nO * nI);
   const int64_t groups = red == 1 ? (int64_t)nb * nO : (red == 2 ? (int64_t)nb * nI : 1);
   int64_t t = red ? 8 : LPB;
@@ -801,7 +821,7 @@ int inner_solve(helm_plan* p, const Level& lv, const InnerIO& io, hipStream_t st
   if (io.rhoL0) {
     int tl, ntl;
     tiles_for(2, lv.nb, lv.nO, lv.nI, lv.nL, &tl, &ntl);
-    s3.red = 2;
+    s3.red = red_l_mode(lv.nb, lv.nI, lv.nL);
     s3.rho0 = io.rhoL0;
     s3.rho1 = io.rhoL1;
     s3.part = part;

@@ -127,6 +127,50 @@ def test_3d_fp64_matches_banded_lu(grid, omega, mask):
     assert np.max(err) <= 1e-9
 
 
+LAYOUT_CASES = [
+    ((8, 8, 9), 6.0, 0b111111),      # 128 lines per block, 8 valid m per block in layout 3
+    ((12, 10, 9), 8.0, 0b111111),
+    ((8, 24, 7), 10.0, 0b110111),
+    ((16, 16, 13), 14.0, 0b111111),
+    ((3, 257, 5), 40.0, 0b111111),   # chirp-z along x2, 257 modes: a last group of one m
+    ((3, 3, 513), 150.0, 0b111111),  # lines of 8 x 64 + 1 rows: the extra row in the partials
+    ((3, 5, 300), 30.0, 0b111111),   # identity padding rows (300 -> 8 x 64)
+]
+
+
+@pytest.mark.parametrize("layout", ["2", "3"])
+@pytest.mark.parametrize("grid,omega,mask", LAYOUT_CASES)
+def test_3d_reduce_over_l_layouts_match_banded_lu(grid, omega, mask, layout, monkeypatch):
+    """Both block layouts of the line solves that reduce over the x_1 modes
+    (slots over l with one m per block, or slots over consecutive m at one l)
+    against the oracle, whatever size picks one by default."""
+    monkeypatch.setenv("HELM_RED_L_LAYOUT", layout)
+    f = inputs.gaussian_batch(grid, [51, 52, 53]).astype(np.complex128)
+    rc, rep, u, h = _run(grid, omega, mask, f)
+    ref = _oracle(grid, h, omega, mask, f)
+    err = fem.rel_error(u.reshape(3, -1), ref.reshape(3, -1))
+    _say("  layout", layout, "rel err", err, "report", rep)
+    assert rc == helm.HELM_OK
+    assert np.max(err) <= 1e-9
+
+
+@pytest.mark.parametrize("layout", ["2", "3"])
+def test_3d_reduce_over_l_layouts_mixed(layout, monkeypatch):
+    monkeypatch.setenv("HELM_RED_L_LAYOUT", layout)
+    grid, omega = (16, 16, 13), 14.0
+    mask = (1 << (2 * len(grid))) - 1
+    f = inputs.gaussian_batch(grid, [54, 55]).astype(np.complex128)
+    rc, rep, u, h = _run(grid, omega, mask, f, precision=helm.PREC_MIXED)
+    ref = _oracle(grid, h, omega, mask, f)
+    err = fem.rel_error(u.reshape(2, -1), ref.reshape(2, -1))
+    res = fem.rel_residual(tuple(grid), h, omega, _abc_tuple(len(grid), mask), u.reshape(2, -1),
+                           f.reshape(2, -1))
+    _say("  layout", layout, "mixed rel err", err, "oracle residual", res, rep)
+    assert rc == helm.HELM_OK
+    assert np.max(res) <= 1e-10
+    assert np.max(err) <= 1e-8
+
+
 @pytest.mark.parametrize("grid,omega", [((64, 77), 35.0), ((16, 16, 13), 14.0), ((1024, 17), 300.0),
                                          ((513, 33), 150.0), ((12, 20, 9), 12.0), ((16, 1025), 300.0),
                                          ((3, 4097), 1200.0), ((512, 17), 150.0)])
