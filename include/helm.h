@@ -23,12 +23,12 @@
  *   - stream is a hipStream_t or NULL for the default stream.
  *   - Every function returns a status code (HELM_OK = 0, negative on error);
  *     no C++ exception crosses this boundary.
- *   - Environment: HELM_RED_L_LAYOUT=2 or 3 fixes how the 3D line solves that
- *     reduce over the x_1 modes assign lines to thread blocks (2: one x_2
- *     mode per block, 3: consecutive x_2 modes per block); unset, the library
- *     picks by size.  Both give the same sums; the variable exists for
- *     testing and tuning and is read whenever a solve is enqueued (a solve
- *     replayed from a captured graph keeps the layout it was captured with).
+ *   - Environment: HELM_RED_L_LAYOUT=3 makes the 3D line solves that reduce
+ *     over the x_1 modes give each thread block consecutive x_2 modes at one
+ *     x_1 mode instead of one x_2 mode over many x_1 modes (2, the default).
+ *     Both give the same sums; the variable exists for testing and tuning
+ *     and is read whenever a solve is enqueued (a solve replayed from a
+ *     captured graph keeps the layout it was captured with).
  */
 #ifndef HELM_H
 #define HELM_H

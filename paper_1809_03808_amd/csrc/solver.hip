@@ -656,33 +656,39 @@ int run_fft(helm_plan* p, const PAxis& a, int sign, bool fp32, const void* in, i
   return HELM_OK;
 }
 
-// Lines per tile: at least 8 lines feed each partial sum (partials stay
-// below 1/4 of an N-sized array).  A reducing launch writes one partial of
-// 2 nL values per block, so it uses about as many blocks as stay resident
-// at once (one 512-thread or two 256-thread blocks per compute unit at the
-// register use of the reducing kernels) and no more; other launches take up
-// to 2048 blocks.
-// Layout of a reduction over l (red 2 or 3, see the line kernel): with at
-// least 1024 groups of LPB consecutive m (b < nb), every block takes LPB
-// adjacent lines per iteration (red 3, all l in one tile); otherwise one m per
-// block with its slots over l (red 2).  HELM_RED_L_LAYOUT=2 or 3 in the
-// environment selects one of them for every size (both compute the same sums).
+// Layout of a reduction over l (red 2 or 3, see the line kernel).  Red 2
+// (one m per block, slots over l) is the default for every size: red 3
+// (slots over consecutive m at one l) measured 0.5% slower at 512^3 x 16,
+// 1.5% slower at 256^3 and 1% faster at 513^3.  HELM_RED_L_LAYOUT=2 or 3 in
+// the environment selects one (both compute the same sums).
 int red_l_mode(int nb, int nI, int nL) {
+  (void)nb;
+  (void)nI;
+  (void)nL;
   const char* env = std::getenv("HELM_RED_L_LAYOUT");
-  if (env && (env[0] == '2' || env[0] == '3') && env[1] == 0) return env[0] - '0';
-  int P, c, NT;
-  lines_geometry(nL, &P, &c, &NT);
-  const int LPB = NT / P;
-  return LPB > 1 && (int64_t)nb * ((nI + LPB - 1) / LPB) >= 1024 ? 3 : 2;
+  if (env && env[0] == '3' && env[1] == 0) return 3;
+  return 2;
 }
 
-void tiles_for(int red, int nb, int nO, int nI, int nL, int* tile, int* ntiles) {
+// Lines per tile and tiles of a line launch; `layout` (2 or 3) only matters
+// for red 2.  At least 8 lines feed each partial sum (partials stay below 1/4
+// of an N-sized array).  A reducing launch writes one partial of 2 nL values
+// per block, so it uses about as many blocks as stay resident at once (one
+// 512-thread or two 256-thread blocks per compute unit at the register use of
+// the reducing kernels) and no more; other launches take up to 2048 blocks.
+// Layout 3 writes one partial per slot and splits the l of every group of
+// consecutive m into as few tiles as give at least 1024 blocks.
+void tiles_for_layout(int red, int layout, int nb, int nO, int nI, int nL, int* tile, int* ntiles) {
   int P, c, NT;
   lines_geometry(nL, &P, &c, &NT);
   const int LPB = NT / P;
-  if (red == 2 && red_l_mode(nb, nI, nL) == 3) {
-    *tile = nO;
-    *ntiles = 1;
+  if (red == 2 && layout == 3) {
+    const int64_t groups = (int64_t)nb * ((nI + LPB - 1) / LPB);
+    int64_t nt = groups >= 1024 ? 1 : (1024 + groups - 1) / groups;
+    if (nt > nO) nt = nO;
+    const int64_t t = (nO + nt - 1) / nt;
+    *tile = (int)t;
+    *ntiles = (int)((nO + t - 1) / t);
     return;
   }
   const int64_t extent = red == 1 ? nI : (red == 2 ? nO : (int64_t)nb * nO * nI);
@@ -697,11 +703,18 @@ void tiles_for(int red, int nb, int nO, int nI, int nL, int* tile, int* ntiles) 
   *ntiles = (int)((extent + t - 1) / t);
 }
 
+void tiles_for(int red, int nb, int nO, int nI, int nL, int* tile, int* ntiles) {
+  tiles_for_layout(red, red == 2 ? red_l_mode(nb, nI, nL) : red, nb, nO, nI, nL, tile, ntiles);
+}
+
+// Partial sums of a reducing launch; for red 2 the larger of the two layouts,
+// so that the buffer fits whichever layout a later solve takes.
 size_t part_elems(int red, int nb, int nO, int nI, int nL) {
-  int tile, nt;
-  tiles_for(red, nb, nO, nI, nL, &tile, &nt);
+  int tile, nt, nt3 = 0;
+  tiles_for_layout(red, 2, nb, nO, nI, nL, &tile, &nt);
+  if (red == 2) tiles_for_layout(red, 3, nb, nO, nI, nL, &tile, &nt3);
   const int64_t groups = red == 1 ? (int64_t)nb * nO : (int64_t)nb * nI;
-  return (size_t)groups * nt * 2 * nL;
+  return (size_t)groups * std::max(nt, nt3) * 2 * nL;
 }
 
 struct Level {  // geometry of one inner 2D solve, batched over (b, l)
