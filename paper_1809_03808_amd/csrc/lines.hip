@@ -478,34 +478,41 @@ __global__ __launch_bounds__(NT) void lines_kernel(LineDev a) {
           if (r < seg) S[stage_pos(si * seg + r)] = make_double2(0, 0);
         }
       }
-      // Rank-2 terms.  The reducing kernels of exact lines with several
-      // lines per block load all rows of a source before combining any into
-      // the staged values, so those loads are in flight together; loads
-      // interleaved with the LDS updates may be issued one by one, each
-      // waited for (measured at 512^3 x 16: 20-25 ms against 10-12 ms per
-      // launch).  The other kernels update row by row, which keeps their
-      // register count and occupancy.
-      if constexpr (RED && !XR && !PAD && P <= 128) {
+      // Rank-2 terms.  The reducing kernels of exact lines load the rows of
+      // a source in batches of NBAT chunk rows before combining any of them
+      // into the staged values, so the loads of a batch are in flight
+      // together; loads interleaved with the LDS updates may be issued one by
+      // one, each waited for (measured at 512^3 x 16: 20-25 ms against
+      // 10-12 ms per launch).  Batches cost registers: all kCMax rows with
+      // several lines per block, 2 at P = 512 (at the register limit; -2% per
+      // launch at 4096^2).  The other kernels update row by row, which keeps
+      // their register count and occupancy (a batch costs the storing
+      // kernels, and the reducing ones at P = 256, an occupancy level).
+      constexpr int NBAT = (RED && !XR && !PAD) ? (P <= 128 ? kCMax : (P == 512 ? 2 : 0)) : 0;
+      if constexpr (NBAT > 0) {
 #pragma unroll
         for (int src = 0; src < 2; ++src) {
           const double2* rows = src == 0 ? po : pi;
           if (!rows) continue;
           const int64_t stride = src == 0 ? (int64_t)a.nI * nL : (int64_t)nL;
           const double2 w0 = src == 0 ? al0 : be0, w1 = src == 0 ? al1 : be1;
-          double2 p0[kCMax], p1[kCMax];
 #pragma unroll
-          for (int jj = 0; jj < kCMax; ++jj) {
-            const int r = jj * 64 + lane, x = wx0 + r;
-            const bool ok = r < seg && x < nL && sv;
-            p0[jj] = ok ? rows[x] : make_double2(0, 0);
-            p1[jj] = ok ? rows[stride + x] : make_double2(0, 0);
-          }
+          for (int j0 = 0; j0 < kCMax; j0 += NBAT) {
+            double2 p0[NBAT], p1[NBAT];
 #pragma unroll
-          for (int jj = 0; jj < kCMax; ++jj) {
-            const int r = jj * 64 + lane, x = wx0 + r;
-            if (r < seg && x < nL && sv) {
-              const int q = stage_pos(si * seg + r);
-              S[q] = cfma(w1, p1[jj], cfma(w0, p0[jj], S[q]));
+            for (int u = 0; u < NBAT; ++u) {
+              const int r = (j0 + u) * 64 + lane, x = wx0 + r;
+              const bool ok = r < seg && x < nL && sv;
+              p0[u] = ok ? rows[x] : make_double2(0, 0);
+              p1[u] = ok ? rows[stride + x] : make_double2(0, 0);
+            }
+#pragma unroll
+            for (int u = 0; u < NBAT; ++u) {
+              const int r = (j0 + u) * 64 + lane, x = wx0 + r;
+              if (r < seg && x < nL && sv) {
+                const int q = stage_pos(si * seg + r);
+                S[q] = cfma(w1, p1[u], cfma(w0, p0[u], S[q]));
+              }
             }
           }
         }
