@@ -483,12 +483,16 @@ __global__ __launch_bounds__(NT) void lines_kernel(LineDev a) {
       // into the staged values, so the loads of a batch are in flight
       // together; loads interleaved with the LDS updates may be issued one by
       // one, each waited for (measured at 512^3 x 16: 20-25 ms against
-      // 10-12 ms per launch).  Batches cost registers: all kCMax rows with
-      // several lines per block, 2 at P = 512 (at the register limit; -2% per
-      // launch at 4096^2).  The other kernels update row by row, which keeps
-      // their register count and occupancy (a batch costs the storing
+      // 10-12 ms per launch).  Batches cost registers: reducing kernels take
+      // all kCMax rows with several lines per block and 2 at P = 512 (at the
+      // register limit; -2% per launch at 4096^2); storing kernels at
+      // P = 16 to 64 take 4 (same occupancy; -11% per storing launch at
+      // 512^3 x 16).  The other kernels update row by row, which keeps their
+      // register count and occupancy (a batch would cost the other storing
       // kernels, and the reducing ones at P = 256, an occupancy level).
-      constexpr int NBAT = (RED && !XR && !PAD) ? (P <= 128 ? kCMax : (P == 512 ? 2 : 0)) : 0;
+      constexpr int NBAT = (XR || PAD) ? 0
+                           : RED     ? (P <= 128 ? kCMax : (P == 512 ? 2 : 0))
+                                     : ((P >= 16 && P <= 64) ? 4 : 0);
       if constexpr (NBAT > 0) {
 #pragma unroll
         for (int src = 0; src < 2; ++src) {
