@@ -478,12 +478,12 @@ __global__ __launch_bounds__(NT) void lines_kernel(LineDev a) {
           if (r < seg) S[stage_pos(si * seg + r)] = make_double2(0, 0);
         }
       }
-      // Rank-2 terms.  The reducing kernels of exact lines load the rows of
-      // a source in batches of NBAT chunk rows before combining any of them
-      // into the staged values, so the loads of a batch are in flight
-      // together; loads interleaved with the LDS updates may be issued one by
-      // one, each waited for (measured at 512^3 x 16: 20-25 ms against
-      // 10-12 ms per launch).  Batches cost registers: reducing kernels take
+      // Rank-2 terms.  Kernels of exact lines load the rows of a source in
+      // batches of NBAT chunk rows before combining any of them into the
+      // staged values, so the loads of a batch are in flight together; loads
+      // interleaved with the LDS updates may be issued one by one, each
+      // waited for (measured at 512^3 x 16: 20-25 ms against 10-12 ms per
+      // reducing launch).  Batches cost registers: reducing kernels take
       // all kCMax rows with several lines per block and 2 at P = 512 (at the
       // register limit; -2% per launch at 4096^2); storing kernels at
       // P = 16 to 64 take 4 (same occupancy; -11% per storing launch at
@@ -522,7 +522,7 @@ __global__ __launch_bounds__(NT) void lines_kernel(LineDev a) {
         }
       } else {
         if (po) {
-  #pragma unroll
+#pragma unroll
           for (int jj = 0; jj < kCMax; ++jj) {
             const int r = jj * 64 + lane, x = wx0 + r;
             if (r < seg && x < nL && sv) {
@@ -534,7 +534,7 @@ __global__ __launch_bounds__(NT) void lines_kernel(LineDev a) {
           }
         }
         if (pi) {
-  #pragma unroll
+#pragma unroll
           for (int jj = 0; jj < kCMax; ++jj) {
             const int r = jj * 64 + lane, x = wx0 + r;
             if (r < seg && x < nL && sv) {
