@@ -487,12 +487,15 @@ __global__ __launch_bounds__(NT) void lines_kernel(LineDev a) {
       // all kCMax rows with several lines per block and 2 at P = 512 (at the
       // register limit; -2% per launch at 4096^2); storing kernels at
       // P = 16 to 64 take 4 (same occupancy; -11% per storing launch at
-      // 512^3 x 16).  The other kernels update row by row, which keeps their
-      // register count and occupancy (a batch would cost the other storing
-      // kernels, and the reducing ones at P = 256, an occupancy level).
+      // 512^3 x 16), and with complex64 storage at P = 512 2, each batch
+      // scheduled on its own (same occupancy; -4% per line launch at 4096^2).
+      // The other kernels update row by row, which keeps their register
+      // count and occupancy (a batch would cost the other storing kernels,
+      // and the reducing ones at P = 256, an occupancy level).
+      constexpr bool SEP = !RED && P == 512 && sizeof(T) == sizeof(float2);
       constexpr int NBAT = (XR || PAD) ? 0
                            : RED     ? (P <= 128 ? kCMax : (P == 512 ? 2 : 0))
-                                     : ((P >= 16 && P <= 64) ? 4 : 0);
+                                     : ((P >= 16 && P <= 64) ? 4 : (SEP ? 2 : 0));
       if constexpr (NBAT > 0) {
 #pragma unroll
         for (int src = 0; src < 2; ++src) {
@@ -518,6 +521,8 @@ __global__ __launch_bounds__(NT) void lines_kernel(LineDev a) {
                 S[q] = cfma(w1, p1[u], cfma(w0, p0[u], S[q]));
               }
             }
+            // keep the next batch's loads after these updates (registers)
+            if constexpr (SEP) __builtin_amdgcn_sched_barrier(0);
           }
         }
       } else {
