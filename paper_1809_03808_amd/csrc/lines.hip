@@ -447,16 +447,20 @@ __global__ __launch_bounds__(NT) void lines_kernel(LineDev a) {
   // entering pivot and reduction weights at the top of the iteration, so
   // those loads are in flight while the right-hand side is staged instead of
   // each being waited for where it is used (-3% per step at 256^3 and
-  // 512^3 x 16; the other kernels lack the registers).
+  // 512^3 x 16); at P = 512 the registers allow sigma and the pivot
+  // (-2% per line launch at 4096^2).  The other kernels lack the registers.
   constexpr bool EARLY = RED && !XR && !PAD && P <= 64;
+  constexpr bool EARLY_SP = RED && !XR && !PAD && P == 512;
   for (int it = 0; it < a.iters; ++it) {
     uint32_t eb = 0, el = 0, em = 0;
     bool evalid = false;
     double2 esig = make_double2(0, 0), eip = make_double2(0, 0), ew0 = eip, ew1 = eip;
-    if constexpr (EARLY) {
+    if constexpr (EARLY || EARLY_SP) {
       evalid = decode_line(a, g, t, LPB, it, slot, eb, el, em);
       esig = line_sigma(a, el, em);
       if (q > 0) eip = a.piv[(int64_t)(el * a.nI + em) * P + q];
+    }
+    if constexpr (EARLY) {
       const uint32_t wi = (a.red == 1) ? em : el;
       ew0 = a.rho0[wi];
       ew1 = a.rho1[wi];
@@ -598,12 +602,12 @@ __global__ __launch_bounds__(NT) void lines_kernel(LineDev a) {
 
     uint32_t b, l, m;
     bool valid;
-    if constexpr (EARLY) {
+    if constexpr (EARLY || EARLY_SP) {
       b = eb; l = el; m = em; valid = evalid;
     } else {
       valid = decode_line(a, g, t, LPB, it, slot, b, l, m);
     }
-    const RowCoef rc = EARLY ? coef_of_sigma(a, esig) : row_coef(a, l, m);
+    const RowCoef rc = (EARLY || EARLY_SP) ? coef_of_sigma(a, esig) : row_coef(a, l, m);
     const double2 moff = make_double2(-rc.off.x, -rc.off.y);  // -e
     double2 z[kCMax];
 #pragma unroll
@@ -630,7 +634,7 @@ __global__ __launch_bounds__(NT) void lines_kernel(LineDev a) {
     // table, then the Thomas recurrence p_x = d_x - e^2 / p_{x-1}.
     // Forward substitution z_x = f_x z_{x-1} + d_x, f_x = -e / p_{x-1}: the
     // lane composes its rows into one affine map.
-    const double2 ip_in = EARLY ? eip : (q > 0 ? a.piv[(int64_t)(l * a.nI + m) * P + q] : make_double2(0, 0));
+    const double2 ip_in = (EARLY || EARLY_SP) ? eip : (q > 0 ? a.piv[(int64_t)(l * a.nI + m) * P + q] : make_double2(0, 0));
     Aff A = aff_ident();
     double2 ipp_last;  // 1/p of the chunk's last row
     {
