@@ -44,7 +44,7 @@ extern "C" {
 #define HELM_EINVAL       -1  /* bad argument: dimension, grid < 3, nrhs < 1, null pointer */
 #define HELM_ENOMEM       -2  /* device or host allocation failed */
 #define HELM_EDEVICE      -3  /* a HIP runtime call failed */
-#define HELM_ESINGULAR    -4  /* the system is singular (e.g. omega = 0 with no absorbing face) */
+#define HELM_ESINGULAR    -4  /* the system is singular or degenerate (omega = 0 is always rejected) */
 #define HELM_ENOCONV      -5  /* refinement did not reach tol within max_iter (u holds the last iterate) */
 #define HELM_ENONFINITE   -6  /* f (or an intermediate residual) holds NaN or Inf */
 #define HELM_EUNSUPPORTED -7  /* valid problem outside what this build implements */
@@ -96,10 +96,10 @@ typedef struct helm_plan helm_plan;
  *   h      host array of dim mesh sizes h_j > 0 (the paper uses h_j = 1/(n_j - 1))
  *   omega  wavenumber (finite)
  *   abc    face mask: bit 2j = low face of axis j is absorbing, bit 2j+1 = high
- *          face; clear bits are Neumann faces.  Each periodised axis (x_1, and
- *          x_2 in 3D) needs the same condition on both of its faces; the last
- *          axis needs at least one absorbing face (else its tridiagonal
- *          systems can be exactly singular).
+ *          face; clear bits are Neumann faces.  Any combination is accepted
+ *          on the periodised axes (x_1, and x_2 in 3D); the last axis needs
+ *          at least one absorbing face (else its tridiagonal systems can be
+ *          exactly singular).
  *   opt    options or NULL for the defaults
  *   out    receives the plan
  * Computes the FP64 1D spectra on the host: closed-form periodic spectra
@@ -109,9 +109,10 @@ typedef struct helm_plan helm_plan;
  * Size limits of this build: the last (line) axis has at most 4097 nodes;
  * a periodised axis of n nodes needs a transform length (n itself for a power
  * of two, else a chirp-z length >= 2n - 1) of at most 2^18.
- * Errors: HELM_EINVAL, HELM_ESINGULAR (omega = 0 and no absorbing face),
- * HELM_EUNSUPPORTED (a periodised axis with mixed face conditions, or a
- * length beyond the limits above), HELM_ENOMEM, HELM_EDEVICE.
+ * Errors: HELM_EINVAL, HELM_ESINGULAR (omega = 0: every absorbing face then
+ * degenerates to a Neumann face and A annihilates the constants, so it is
+ * rejected whatever the mask), HELM_EUNSUPPORTED (no absorbing face on the
+ * last axis, or a length beyond the limits above), HELM_ENOMEM, HELM_EDEVICE.
  */
 int helm_setup(int dim, const int64_t* grid, const double* h, double omega,
                uint32_t abc, const helm_options* opt, helm_plan** out);

@@ -17,11 +17,18 @@ What it computes, in complex128:
   module is that plain definition.
 * ``eigen`` -- the dense generalized eigenproblem K_1 V_1 = M_1 V_1 Lambda^A_1
   of eq. (EVP1a) with the normalisation V^T M V = I of eq. (EVPcondA), solved by
-  QZ (scipy.linalg.eig), and the periodic auxiliary matrices of eqs.
-  (matrixKper), (matrixMper).
+  QZ (scipy.linalg.eig), or for long axes by the flip-symmetry split and a
+  Cholesky reduction to LAPACK zgeev; and the periodic auxiliary matrices of
+  eqs. (matrixKper), (matrixMper).
+* ``sov``   -- a second direct solver for grids whose band is too wide for
+  banded LU: dense separation of variables with the absorbing-boundary
+  eigenvectors (eqs. (A2Dinv), (A3Dinv)) and one pivoted tridiagonal solve
+  (LAPACK zgtsv) per mode, optionally refined with the residual of ``fem``.
 
 Each function is pinned by tests under ``tests/test_oracle_*.py`` against facts
 that do not come from the oracle itself: brute-force dense solves on tiny grids,
+banded LU against the separation of variables and vice versa, QZ against the
+reduced eigenproblems,
 closed-form eigenvalues of the Neumann, Dirichlet and periodic 1D pencils,
 exact symmetry of A, the closed-form interior 9-point stencil, and O(h^2)
 convergence to a manufactured solution that satisfies the absorbing boundary
@@ -29,4 +36,4 @@ condition exactly.  Parity against numbers printed in the paper is unpinned:
 the paper prints timings only, no solution values, errors or residuals.
 """
 
-from . import fem, eigen  # noqa: F401
+from . import fem, eigen, sov  # noqa: F401

@@ -103,17 +103,64 @@ def to_banded(A, bw):
     return ab
 
 
-def solve(grid, h, omega, abc, f):
+def operator_in_order(grid, h, omega, abc, perm):
+    """A with its unknowns numbered with the axes in the order ``perm``
+    (slowest first): the same Kronecker terms as eqs. (A2D), (A3D), each
+    term's 1D factors taken in that order.  perm = (0, ..., d-1) is
+    ``operator``; any other order is a symmetric permutation P A P^T of it."""
+    d = len(grid)
+    pairs = [_axis_pair(grid, h, omega, abc, j) for j in range(d)]
+    K = [k for k, _ in pairs]
+    M = [m for _, m in pairs]
+    S1 = K[0] - omega ** 2 * M[0]
+    if d == 2:
+        terms = [(S1, M[1]), (M[0], K[1])]
+    elif d == 3:
+        terms = [(S1, M[1], M[2]), (M[0], K[1], M[2]), (M[0], M[1], K[2])]
+    else:
+        raise ValueError("dimension must be 2 or 3")
+    A = None
+    for t in terms:
+        T = t[perm[0]]
+        for j in perm[1:]:
+            T = sp.kron(T, t[j])
+        A = T if A is None else A + T
+    A = sp.csr_matrix(A)
+    A.eliminate_zeros()
+    return A
+
+
+def narrowest_order(grid):
+    """Axis order (slowest first) with the smallest half bandwidth: the
+    longest axis slowest, the shortest fastest."""
+    return tuple(sorted(range(len(grid)), key=lambda j: (-grid[j], j)))
+
+
+def solve(grid, h, omega, abc, f, order=None):
     """u = A^{-1} f by banded LU with partial pivoting (LAPACK zgbsv via
     scipy.linalg.solve_banded), complex128.  ``f`` has shape (N,) or
-    (nrhs, N); the result has the same shape."""
-    A = operator(grid, h, omega, abc)
-    bw = bandwidth(grid)
-    ab = to_banded(A, bw)
+    (nrhs, N), C-ordered with x_1 slowest; the result has the same shape.
+
+    The band is stored in the unknown numbering of ``order`` (default: the
+    narrowest, see ``narrowest_order``); renumbering the unknowns is a
+    symmetric permutation, so the solution is the same vector, and a grid
+    with a long last axis keeps a narrow band."""
+    grid = tuple(int(n) for n in grid)
+    d = len(grid)
+    perm = tuple(order) if order is not None else narrowest_order(grid)
     f = np.asarray(f, dtype=np.complex128)
-    b = f.T if f.ndim == 2 else f
-    u = sla.solve_banded((bw, bw), ab, b, overwrite_ab=True, check_finite=True)
-    return u.T if f.ndim == 2 else u
+    F = np.atleast_2d(f).reshape((-1,) + grid)
+    nr = F.shape[0]
+    Fp = F.transpose((0,) + tuple(j + 1 for j in perm)).reshape(nr, -1)
+    gp = tuple(grid[j] for j in perm)
+    A = operator_in_order(grid, h, omega, abc, perm)
+    bw = bandwidth(gp)
+    ab = to_banded(A, bw)
+    up = sla.solve_banded((bw, bw), ab, Fp.T, overwrite_ab=True, check_finite=True).T
+    inv = np.argsort(perm)
+    U = up.reshape((nr,) + gp).transpose((0,) + tuple(int(j) + 1 for j in inv))
+    U = np.ascontiguousarray(U).reshape(nr, -1)
+    return U if f.ndim == 2 else U[0]
 
 
 # ---------------------------------------------------------------------------

@@ -139,3 +139,39 @@ def test_batch_uneven_sides_vs_banded_lu():
     batch.close()
     for p in plans:
         p.close()
+
+
+def test_batch_full_sides_by_oracle():
+    """The uneven batch's own sides 513, 1025 and 2049 (chirp-z lengths 1152,
+    2304 and 4608; lines of 8 P + 1 rows), 8-20 points per wavelength, 2
+    right-hand sides each, mixed precision: every problem by the oracle
+    residual over the whole array, and one right-hand side per problem by its
+    error against the separation-of-variables oracle."""
+    from oracle import sov
+    probs = [((513, 513), inputs.omega_for_ppw(513, 8.3)), ((1025, 1025), inputs.omega_for_ppw(1025, 19.0)),
+             ((2049, 2049), inputs.omega_for_ppw(2049, 11.7)), ((513, 513), inputs.omega_for_ppw(513, 15.2))]
+    plans, fs, us, hosts = [], [], [], []
+    for i, (grid, omega) in enumerate(probs):
+        plans.append(helm.Plan(grid, inputs.spacing(grid), omega, precision=helm.PREC_MIXED))
+        f = inputs.gaussian_batch(grid, [inputs.rhs_seed(4, 70 + i, r) for r in range(2)])
+        hosts.append(f)
+        fs.append(torch.from_numpy(f).cuda())
+        us.append(torch.empty_like(fs[-1]))
+    batch = helm.Batch(plans, max_nrhs=2)
+    batch.solve(fs, us)
+    batch.solve(fs, us)  # a replay of the captured graph
+    abc = ((True, True), (True, True))
+    for i, (grid, omega) in enumerate(probs):
+        rep = batch.report(i)
+        h = inputs.spacing(grid)
+        u = us[i].cpu().numpy().reshape(2, -1)
+        f = hosts[i].reshape(2, -1)
+        res = fem.rel_residual(grid, h, omega, abc, u, f)
+        ur = sov.solve(grid, h, omega, abc, f[0], refine=1)
+        err = float(np.linalg.norm(u[0] - ur) / np.linalg.norm(ur))
+        _say(f"  {grid} omega {omega:.2f}: oracle residual {np.max(res):.2e}, error (rhs 0) {err:.2e}, {rep}")
+        assert rep["status"] == helm.HELM_OK and rep["rel_residual_max"] <= 1e-10
+        assert np.max(res) <= 1e-10 and err <= 1e-8
+    batch.close()
+    for p in plans:
+        p.close()

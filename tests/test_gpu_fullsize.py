@@ -1,15 +1,28 @@
-"""Full-size workloads on the GPU, checked by properties the CPU oracle can
-evaluate at any size: the relative residual ||f - A u|| / ||f|| computed by the
-oracle's own matrix-free operator (complex128, numpy/scipy), and agreement of
-the FP64 and the mixed-precision refined solutions.  Banded LU is infeasible
-here (about 3.3 TB of band at 4096^2)."""
+"""Full-size workloads on the GPU, checked by the CPU oracle at full size.
+
+Banded LU is infeasible here (about 3.3 TB of band at 4096^2), so each
+workload is checked by
+  * the relative residual ||f - A u|| / ||f|| over the whole array, from the
+    oracle's own matrix-free operator (complex128, numpy/scipy);
+  * the relative error ||u - u_ref|| / ||u_ref|| against the second oracle,
+    the dense separation of variables (eqs. (A2Dinv), (A3Dinv)) with one
+    refinement step, on one right-hand side; that reference is itself
+    certified by its oracle residual;
+  * the first-solve residual the device reports, against a fixed bound, so
+    that a regression in the direct solve cannot hide behind refinement;
+  * bit-equality of the repeated (captured-graph) solves that bench.py times
+    with the first solve.
+Inputs are drawn on the device with torch's seeded generator and copied to
+the host for the oracle.
+"""
 
 import sys
+import time
 
 import numpy as np
 import pytest
 
-from oracle import fem
+from oracle import fem, sov
 from paper_1809_03808_amd import helm, inputs
 
 pytestmark = pytest.mark.gpu
@@ -20,16 +33,23 @@ def _say(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def _solve(wl, precision, nrhs=None):
-    grid, omega = wl["grid"], wl["omega"]
+def _abc(dim):
+    return ((True, True),) * dim
+
+
+def _inputs(wl, nrhs=None):
     nrhs = nrhs or wl["nrhs"]
+    seeds = [inputs.rhs_seed(wl["config"], 0, r) for r in range(nrhs)]
+    return inputs.gaussian_device(wl["grid"], seeds, "cuda")
+
+
+def _solve(wl, f, precision, check=True):
+    grid, omega = wl["grid"], wl["omega"]
     h = inputs.spacing(grid)
     mask = (1 << (2 * len(grid))) - 1
-    seeds = [inputs.rhs_seed(wl["config"], 0, r) for r in range(nrhs)]
-    f = inputs.gaussian_device(grid, seeds, "cuda")
     u = torch.empty_like(f)
-    _say("full-size", grid, "prec", precision, "nrhs", nrhs)
-    with helm.Plan(grid, h, omega, mask, precision=precision) as plan:
+    _say("full-size", grid, "prec", precision, "check", check, "nrhs", f.shape[0])
+    with helm.Plan(grid, h, omega, mask, precision=precision, check=check) as plan:
         rc = plan.solve(f, u, raise_on_error=False)
         rep = plan.report()
         # the launch configuration bench.py times: repeats of the same call
@@ -45,49 +65,116 @@ def _solve(wl, precision, nrhs=None):
         del u0
     torch.cuda.synchronize()
     _say("  report", rep)
-    return rc, rep, f, u, h
+    return rc, rep, u
 
 
-def _abc(dim):
-    return ((True, True),) * dim
+_REF = {}
 
 
-def test_2d_4096_fp64_residual_by_oracle():
+def _reference(name, wl, f0):
+    """Dense separation of variables (one refinement step) for one RHS,
+    computed once per workload and certified by its oracle residual."""
+    grid, omega = wl["grid"], wl["omega"]
+    h = inputs.spacing(grid)
+    if name in _REF:
+        fr, ur = _REF[name]
+        assert np.array_equal(fr, f0)
+        return ur
+    t0 = time.time()
+    ur = sov.solve(grid, h, omega, _abc(len(grid)), f0, refine=1)
+    res = fem.rel_residual(grid, h, omega, _abc(len(grid)), ur[None], f0[None])[0]
+    _say(f"  separation-of-variables reference: {time.time() - t0:.1f} s, own oracle residual {res:.2e}")
+    assert res <= 1e-13
+    _REF[name] = (f0, ur)
+    return ur
+
+
+def _oracle_checks(name, wl, f, u, rhs=0):
+    """Oracle residual over the whole array and error against the reference
+    for right-hand side `rhs`; returns (residual, error)."""
+    grid, omega = wl["grid"], wl["omega"]
+    h = inputs.spacing(grid)
+    f0 = f[rhs].cpu().numpy().reshape(-1)
+    u0 = u[rhs].cpu().numpy().reshape(-1)
+    t0 = time.time()
+    res = fem.rel_residual(grid, h, omega, _abc(len(grid)), u0[None], f0[None])[0]
+    _say(f"  oracle residual {res:.3e} ({time.time() - t0:.1f} s)")
+    ur = _reference(name, wl, f0)
+    err = float(np.linalg.norm(u0 - ur) / np.linalg.norm(ur))
+    _say(f"  rel. error against the separation-of-variables oracle: {err:.3e}")
+    return res, err
+
+
+# ---------------------------------------------------------------------------
+# 2D 4096^2, 10 points per wavelength, one RHS
+# ---------------------------------------------------------------------------
+
+def test_2d_4096_fp64_checked():
     wl = inputs.workload("2d_4096_ppw10")
-    rc, rep, f, u, h = _solve(wl, helm.PREC_FP64)
+    f = _inputs(wl)
+    rc, rep, u = _solve(wl, f, helm.PREC_FP64)
     assert rc == helm.HELM_OK
-    fc = f.cpu().numpy().reshape(1, -1)
-    uc = u.cpu().numpy().reshape(1, -1)
-    res = fem.rel_residual(wl["grid"], h, wl["omega"], _abc(2), uc, fc)
-    _say("  oracle residual", res)
-    assert res[0] <= 1e-10
-    # the device FP64 residual agrees with the oracle's (to rounding when both
-    # sit at the ~1e-14 floor)
-    assert abs(res[0] - rep["rel_residual_max"]) <= 1e-2 * res[0] + 1e-14
+    # first-solve residual measured at 2.7e-9 (one refinement step follows)
+    assert 0 <= rep["rel_residual_first"] <= 1e-8
+    res, err = _oracle_checks("2d_4096_ppw10", wl, f, u)
+    assert res <= 1e-10 and err <= 1e-9
+    # the device FP64 residual agrees with the oracle's
+    assert abs(res - rep["rel_residual_max"]) <= 1e-2 * res + 1e-14
 
 
-def test_2d_4096_mixed_matches_fp64():
+def test_2d_4096_fp64_plain_error():
+    """The plain FP64 solve (one pass of the method, no refinement): its error
+    against the reference is stated; the bound pins today's value."""
     wl = inputs.workload("2d_4096_ppw10")
-    rc64, rep64, f, u64, h = _solve(wl, helm.PREC_FP64)
-    rc32, rep32, f2, u32, _ = _solve(wl, helm.PREC_MIXED)
-    assert rc64 == helm.HELM_OK and rc32 == helm.HELM_OK
-    assert torch.equal(f, f2)
-    d = (torch.linalg.vector_norm(u32 - u64) / torch.linalg.vector_norm(u64)).item()
-    _say("  ||u_mixed - u_fp64|| / ||u_fp64|| =", d)
-    assert rep32["rel_residual_max"] <= 1e-10
-    assert d <= 1e-8
+    f = _inputs(wl)
+    rc, rep, u = _solve(wl, f, helm.PREC_FP64, check=False)
+    assert rc == helm.HELM_OK and rep["iterations"] == 0
+    res, err = _oracle_checks("2d_4096_ppw10", wl, f, u)
+    _say(f"  PLAIN FP64 4096^2: residual {res:.3e} error {err:.3e}")
+    assert res <= 1e-8 and err <= 1e-6
 
 
-def test_3d_256_mixed_residual_by_oracle():
+def test_2d_4096_mixed():
+    wl = inputs.workload("2d_4096_ppw10")
+    f = _inputs(wl)
+    rc, rep, u = _solve(wl, f, helm.PREC_MIXED)
+    assert rc == helm.HELM_OK and rep["rel_residual_max"] <= 1e-10
+    assert 0 <= rep["rel_residual_first"] <= 1e-4
+    res, err = _oracle_checks("2d_4096_ppw10", wl, f, u)
+    assert res <= 1e-10 and err <= 1e-8
+
+
+# ---------------------------------------------------------------------------
+# 3D 256^3, 10 points per wavelength, one RHS
+# ---------------------------------------------------------------------------
+
+def test_3d_256_fp64():
     wl = inputs.workload("3d_256_ppw10")
-    rc, rep, f, u, h = _solve(wl, helm.PREC_MIXED)
+    f = _inputs(wl)
+    rc, rep, u = _solve(wl, f, helm.PREC_FP64)
     assert rc == helm.HELM_OK
-    fc = f.cpu().numpy().reshape(1, -1)
-    uc = u.cpu().numpy().reshape(1, -1)
-    res = fem.rel_residual(wl["grid"], h, wl["omega"], _abc(3), uc, fc)
-    _say("  oracle residual", res)
-    assert res[0] <= 1e-10
+    assert 0 <= rep["rel_residual_first"] <= 1e-9
+    res, err = _oracle_checks("3d_256_ppw10", wl, f, u)
+    assert res <= 1e-10 and err <= 1e-9
+    rc, rep, u = _solve(wl, f, helm.PREC_FP64, check=False)
+    res, err = _oracle_checks("3d_256_ppw10", wl, f, u)
+    _say(f"  PLAIN FP64 256^3: residual {res:.3e} error {err:.3e}")
+    assert rc == helm.HELM_OK and res <= 1e-9 and err <= 1e-8
 
+
+def test_3d_256_mixed():
+    wl = inputs.workload("3d_256_ppw10")
+    f = _inputs(wl)
+    rc, rep, u = _solve(wl, f, helm.PREC_MIXED)
+    assert rc == helm.HELM_OK and rep["rel_residual_max"] <= 1e-10 and rep["iterations"] >= 1
+    assert 0 <= rep["rel_residual_first"] <= 1e-4
+    res, err = _oracle_checks("3d_256_ppw10", wl, f, u)
+    assert res <= 1e-10 and err <= 1e-8
+
+
+# ---------------------------------------------------------------------------
+# 3D 512^3, 10 points per wavelength, 16 RHS in one solve
+# ---------------------------------------------------------------------------
 
 def _sampled_rows(grid, h, omega, u, points):
     """(A u) at a few nodes, from the oracle's 1D matrices (eqs. (matrixK),
@@ -109,57 +196,68 @@ def _sampled_rows(grid, h, omega, u, points):
     return np.array(out)
 
 
-def test_3d_512x16_fp64_sampled_rows_by_oracle():
-    """The 512^3 x 16 workload at full size: the device certifies ||f - Au||/||f||
-    <= 1e-10 for every RHS; on sampled nodes (corners, faces, interior) of three
-    right-hand sides, the device residual r = f - A u agrees with the oracle's
-    rows of A to 1e-12 of the RMS load, and is itself below 1e-9 of it."""
-    wl = inputs.workload("3d_512_ppw10_x16")
-    rc, rep, f, u, h = _solve(wl, helm.PREC_FP64)
-    assert rc == helm.HELM_OK and rep["rel_residual_max"] <= 1e-10
-    grid = wl["grid"]
+def _sample_points(grid, seed):
     n1, n2, n3 = grid
-    rng = np.random.default_rng(7)
+    rng = np.random.default_rng(seed)
     pts = [(0, 0, 0), (n1 - 1, n2 - 1, n3 - 1), (0, n2 // 2, n3 - 1), (n1 // 2, 0, 5)]
     pts += [(int(rng.integers(0, n1)), int(rng.integers(0, n2)), int(rng.integers(0, n3))) for _ in range(8)]
-    with helm.Plan(grid, h, wl["omega"]) as plan:
-        for b in (0, 7, 15):
-            ub, fb = u[b:b + 1].contiguous(), f[b:b + 1].contiguous()
-            rb = torch.empty_like(ub)
-            plan.residual(ub, fb, rb)
-            torch.cuda.synchronize()
-            uh = ub[0].cpu().numpy()
-            fh = fb[0].cpu().numpy()
-            rh = rb[0].cpu().numpy()
-            rms = np.sqrt(np.mean(np.abs(fh) ** 2))
-            au = _sampled_rows(grid, h, wl["omega"], uh, pts)
-            r_or = np.array([fh[p] for p in pts]) - au
-            r_dev = np.array([rh[p] for p in pts])
-            _say(f"  rhs {b}: max |r_oracle| / rms(f) = {np.max(np.abs(r_or)) / rms:.2e}, "
-                 f"max |r_dev - r_oracle| / rms(f) = {np.max(np.abs(r_dev - r_or)) / rms:.2e}")
-            assert np.max(np.abs(r_dev - r_or)) <= 1e-12 * rms
-            assert np.max(np.abs(r_or)) <= 1e-9 * rms
-            del ub, fb, rb
+    return pts
 
 
-def test_3d_512x16_mixed_sampled_rows_by_oracle():
-    """The 512^3 x 16 workload at full size on the complex64 + FP64 refinement
-    path (whose line kernels batch their rank-2 loads): the device certifies
-    ||f - Au||/||f|| <= 1e-10 for every RHS, repeats reproduce the first
-    solve, and on sampled nodes of two right-hand sides the oracle's rows of A
-    give a residual below 1e-8 of the RMS load."""
+def test_3d_512x16_fp64():
+    """All 16 right-hand sides certified by the device residual; RHS 0 by the
+    oracle residual over the whole array, the device residual element-wise
+    against the oracle's, and the error against the reference; RHS 15 by the
+    oracle's rows of A on sampled nodes."""
     wl = inputs.workload("3d_512_ppw10_x16")
-    rc, rep, f, u, h = _solve(wl, helm.PREC_MIXED)
+    f = _inputs(wl)
+    rc, rep, u = _solve(wl, f, helm.PREC_FP64)
+    assert rc == helm.HELM_OK and rep["rel_residual_max"] <= 1e-10
+    # first-solve residual measured at 1.1e-10 (one refinement step follows)
+    assert 0 <= rep["rel_residual_first"] <= 1e-9
+    grid, omega = wl["grid"], wl["omega"]
+    h = inputs.spacing(grid)
+    with helm.Plan(grid, h, omega) as plan:
+        ub, fb = u[0:1].contiguous(), f[0:1].contiguous()
+        rb = torch.empty_like(ub)
+        plan.residual(ub, fb, rb)
+        torch.cuda.synchronize()
+        r_dev = rb[0].cpu().numpy().reshape(-1)
+        del ub, fb, rb
+    f0 = f[0].cpu().numpy().reshape(-1)
+    u0 = u[0].cpu().numpy().reshape(-1)
+    r_or = fem.residual(grid, h, omega, _abc(3), u0, f0)
+    rms = np.sqrt(np.mean(np.abs(f0) ** 2))
+    dmax = np.max(np.abs(r_dev - r_or)) / rms
+    _say(f"  max |r_dev - r_oracle| / rms(f) over all nodes: {dmax:.2e}")
+    assert dmax <= 1e-12
+    del r_dev, r_or
+    res, err = _oracle_checks("3d_512_ppw10_x16", wl, f, u)
+    assert res <= 1e-10 and err <= 1e-9
+    uh, fh = u[15].cpu().numpy(), f[15].cpu().numpy()
+    pts = _sample_points(grid, 7)
+    r_s = np.array([fh[p] for p in pts]) - _sampled_rows(grid, h, omega, uh, pts)
+    rms15 = np.sqrt(np.mean(np.abs(fh) ** 2))
+    _say(f"  rhs 15: max |r_oracle| / rms(f) on sampled nodes = {np.max(np.abs(r_s)) / rms15:.2e}")
+    assert np.max(np.abs(r_s)) <= 1e-9 * rms15
+
+
+def test_3d_512x16_mixed():
+    """The complex64 + FP64 refinement path at 512^3 x 16: RHS 0 by the
+    oracle residual over the whole array and the error against the
+    reference, RHS 15 by the oracle's rows of A on sampled nodes."""
+    wl = inputs.workload("3d_512_ppw10_x16")
+    f = _inputs(wl)
+    rc, rep, u = _solve(wl, f, helm.PREC_MIXED)
     assert rc == helm.HELM_OK and rep["rel_residual_max"] <= 1e-10 and rep["iterations"] >= 1
-    grid = wl["grid"]
-    n1, n2, n3 = grid
-    rng = np.random.default_rng(11)
-    pts = [(0, 0, 0), (n1 - 1, n2 - 1, n3 - 1), (n1 - 1, 0, n3 // 2), (3, n2 // 2, 0)]
-    pts += [(int(rng.integers(0, n1)), int(rng.integers(0, n2)), int(rng.integers(0, n3))) for _ in range(8)]
-    for b in (0, 15):
-        uh = u[b].cpu().numpy()
-        fh = f[b].cpu().numpy()
-        rms = np.sqrt(np.mean(np.abs(fh) ** 2))
-        r_or = np.array([fh[p] for p in pts]) - _sampled_rows(grid, h, wl["omega"], uh, pts)
-        _say(f"  rhs {b}: max |r_oracle| / rms(f) = {np.max(np.abs(r_or)) / rms:.2e}")
-        assert np.max(np.abs(r_or)) <= 1e-8 * rms
+    assert 0 <= rep["rel_residual_first"] <= 1e-4
+    res, err = _oracle_checks("3d_512_ppw10_x16", wl, f, u)
+    assert res <= 1e-10 and err <= 1e-8
+    grid, omega = wl["grid"], wl["omega"]
+    h = inputs.spacing(grid)
+    uh, fh = u[15].cpu().numpy(), f[15].cpu().numpy()
+    pts = _sample_points(grid, 11)
+    r_s = np.array([fh[p] for p in pts]) - _sampled_rows(grid, h, omega, uh, pts)
+    rms15 = np.sqrt(np.mean(np.abs(fh) ** 2))
+    _say(f"  rhs 15: max |r_oracle| / rms(f) on sampled nodes = {np.max(np.abs(r_s)) / rms15:.2e}")
+    assert np.max(np.abs(r_s)) <= 1e-8 * rms15

@@ -1,8 +1,11 @@
 """GPU parity of the fast solver (through the C ABI) against the CPU oracle.
 
 Small and ragged grids are compared element by element with the banded-LU
-oracle; the bar is relative error <= 1e-9 for the FP64 path and relative
+oracle; the bar is relative error <= 1e-9 for the plain FP64 solve (one pass
+of the three steps, no residual check and no refinement) and relative
 residual <= 1e-10 (plus error <= 1e-8) for the mixed-precision refined path.
+Line lengths cover every lane count P of the line kernels in each of their
+three forms: exactly 8 P rows, 8 P + 1 rows, and shorter lines padded to 8 P.
 """
 
 import sys
@@ -26,10 +29,10 @@ def _abc_tuple(dim, mask):
     return tuple(((mask >> (2 * j)) & 1 == 1, (mask >> (2 * j + 1)) & 1 == 1) for j in range(dim))
 
 
-def _run(grid, omega, mask, f, precision=helm.PREC_FP64, check=True):
+def _run(grid, omega, mask, f, precision=helm.PREC_FP64, check=True, h=None):
     grid = tuple(grid)
-    h = inputs.spacing(grid)
-    _say("case", grid, omega, bin(mask), "prec", precision, "nrhs", f.shape[0])
+    h = inputs.spacing(grid) if h is None else tuple(h)
+    _say("case", grid, omega, bin(mask), "prec", precision, "check", check, "nrhs", f.shape[0])
     plan = helm.Plan(grid, h, omega, mask, precision=precision, check=check)
     fd = torch.from_numpy(f).to("cuda")
     ud = torch.empty_like(fd)
@@ -75,14 +78,88 @@ CASES_2D = [
 
 @pytest.mark.parametrize("grid,omega,mask", CASES_2D)
 def test_2d_fp64_matches_banded_lu(grid, omega, mask):
+    """Plain FP64 solve (no check, no refinement) against banded LU."""
     f = inputs.gaussian_batch(grid, [11, 12]).astype(np.complex128)
-    rc, rep, u, h = _run(grid, omega, mask, f)
+    rc, rep, u, h = _run(grid, omega, mask, f, check=False)
     ref = _oracle(grid, h, omega, mask, f)
     err = fem.rel_error(u.reshape(2, -1), ref.reshape(2, -1))
-    _say("  rel err", err, "report", rep)
+    _say("  plain rel err", err, "report", rep)
     assert rc == helm.HELM_OK
+    assert rep["iterations"] == 0 and rep["rel_residual_max"] == -1
     assert np.max(err) <= 1e-9
-    assert rep["rel_residual_max"] <= 1e-10
+
+
+@pytest.mark.parametrize("grid,omega,mask", CASES_2D[:8] + CASES_2D[-3:])
+def test_2d_fp64_checked_solve_reports(grid, omega, mask):
+    """With the check on, the report's first-solve residual is the plain
+    solve's, and the returned u meets tol by the oracle's own residual."""
+    f = inputs.gaussian_batch(grid, [13, 14]).astype(np.complex128)
+    rc, rep, u, h = _run(grid, omega, mask, f, check=True)
+    ref = _oracle(grid, h, omega, mask, f)
+    err = fem.rel_error(u.reshape(2, -1), ref.reshape(2, -1))
+    res = fem.rel_residual(tuple(grid), h, omega, _abc_tuple(len(grid), mask), u.reshape(2, -1),
+                           f.reshape(2, -1))
+    _say("  checked rel err", err, "oracle residual", res, "report", rep)
+    assert rc == helm.HELM_OK
+    assert 0 <= rep["rel_residual_first"] and rep["rel_residual_max"] <= 1e-10
+    assert np.max(res) <= 1e-10 and np.max(err) <= 1e-9
+    assert rep["iterations"] == 0 or rep["rel_residual_first"] > 1e-10
+    assert abs(np.max(res) - rep["rel_residual_max"]) <= 0.05 * np.max(res) + 1e-15
+
+
+# Lines of exactly 8 P rows for every lane count P = 1 ... 512 (the geometry
+# of the full-size workloads: 4096 rows at 4096^2, 512 at 512^3, 256 at
+# 256^3), on thin strips with the same mesh size on every axis and about ten
+# points per wavelength.
+EXACT_2D = [(5, 8), (4, 16), (3, 32), (5, 64), (4, 128), (3, 256), (4, 512), (3, 1024), (5, 2048),
+            (4, 4096)]
+EXACT_3D = [(4, 4, 64), (4, 3, 128), (3, 4, 256), (3, 20, 256), (3, 4, 512), (5, 12, 512), (3, 3, 1024),
+            (3, 3, 2048), (3, 3, 4096)]
+
+
+def _strip(grid):
+    hh = 1.0 / (grid[-1] - 1)
+    return (hh,) * len(grid), 2 * np.pi / (10.0 * hh)
+
+
+@pytest.mark.parametrize("prec", [helm.PREC_FP64, helm.PREC_MIXED])
+@pytest.mark.parametrize("grid", EXACT_2D)
+def test_2d_exact_lines_match_banded_lu(grid, prec):
+    h, omega = _strip(grid)
+    mask = 0b1111
+    f = inputs.gaussian_batch(grid, [61, 62]).astype(np.complex128)
+    rc, rep, u, _ = _run(grid, omega, mask, f, precision=prec, check=False, h=h)
+    ref = _oracle(grid, h, omega, mask, f)
+    err = fem.rel_error(u.reshape(2, -1), ref.reshape(2, -1))
+    res = fem.rel_residual(tuple(grid), h, omega, _abc_tuple(2, mask), u.reshape(2, -1), f.reshape(2, -1))
+    _say("  exact-line rel err", err, "oracle residual", res, "report", rep)
+    assert rc == helm.HELM_OK
+    if prec == helm.PREC_FP64:
+        assert np.max(err) <= 1e-9
+    else:
+        assert np.max(res) <= 1e-10 and np.max(err) <= 1e-8
+
+
+@pytest.mark.parametrize("layout", ["2", "3"])
+@pytest.mark.parametrize("prec", [helm.PREC_FP64, helm.PREC_MIXED])
+@pytest.mark.parametrize("grid", EXACT_3D)
+def test_3d_exact_lines_match_banded_lu(grid, prec, layout, monkeypatch):
+    """Every reducing and storing kernel of exact lines in 3D, under both
+    block layouts of the reductions over the x_1 modes."""
+    monkeypatch.setenv("HELM_RED_L_LAYOUT", layout)
+    h, omega = _strip(grid)
+    mask = 0b111111
+    f = inputs.gaussian_batch(grid, [63, 64]).astype(np.complex128)
+    rc, rep, u, _ = _run(grid, omega, mask, f, precision=prec, check=False, h=h)
+    ref = _oracle(grid, h, omega, mask, f)
+    err = fem.rel_error(u.reshape(2, -1), ref.reshape(2, -1))
+    res = fem.rel_residual(tuple(grid), h, omega, _abc_tuple(3, mask), u.reshape(2, -1), f.reshape(2, -1))
+    _say("  exact-line layout", layout, "rel err", err, "oracle residual", res, "report", rep)
+    assert rc == helm.HELM_OK
+    if prec == helm.PREC_FP64:
+        assert np.max(err) <= 1e-9
+    else:
+        assert np.max(res) <= 1e-10 and np.max(err) <= 1e-8
 
 
 def test_c1_128_omega80_point_source():
@@ -91,7 +168,7 @@ def test_c1_128_omega80_point_source():
     w = inputs.workload("2d_128_w80")
     grid = w["grid"]
     f = (inputs.gaussian(grid, inputs.rhs_seed(1, 0, 0)) + inputs.point_source(grid))[None]
-    rc, rep, u, h = _run(grid, w["omega"], inputs.ALL_ABC_2D, f)
+    rc, rep, u, h = _run(grid, w["omega"], inputs.ALL_ABC_2D, f, check=False)
     ref = _oracle(grid, h, w["omega"], inputs.ALL_ABC_2D, f)
     err = fem.rel_error(u.reshape(1, -1), ref.reshape(1, -1))
     res = fem.rel_residual(grid, h, w["omega"], _abc_tuple(2, inputs.ALL_ABC_2D), u.reshape(1, -1),
@@ -118,8 +195,9 @@ CASES_3D = [
 
 @pytest.mark.parametrize("grid,omega,mask", CASES_3D)
 def test_3d_fp64_matches_banded_lu(grid, omega, mask):
+    """Plain FP64 solve (no check, no refinement) against banded LU."""
     f = inputs.gaussian_batch(grid, [21, 22]).astype(np.complex128)
-    rc, rep, u, h = _run(grid, omega, mask, f)
+    rc, rep, u, h = _run(grid, omega, mask, f, check=False)
     ref = _oracle(grid, h, omega, mask, f)
     err = fem.rel_error(u.reshape(2, -1), ref.reshape(2, -1))
     _say("  rel err", err, "report", rep)
@@ -146,7 +224,7 @@ def test_3d_reduce_over_l_layouts_match_banded_lu(grid, omega, mask, layout, mon
     against the oracle, whatever size picks one by default."""
     monkeypatch.setenv("HELM_RED_L_LAYOUT", layout)
     f = inputs.gaussian_batch(grid, [51, 52, 53]).astype(np.complex128)
-    rc, rep, u, h = _run(grid, omega, mask, f)
+    rc, rep, u, h = _run(grid, omega, mask, f, check=False)
     ref = _oracle(grid, h, omega, mask, f)
     err = fem.rel_error(u.reshape(3, -1), ref.reshape(3, -1))
     _say("  layout", layout, "rel err", err, "report", rep)
