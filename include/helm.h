@@ -138,6 +138,34 @@ int helm_setup(int dim, const int64_t* grid, const double* h, double omega,
  */
 int helm_solve(helm_plan* p, const void* f, void* u, int nrhs, void* stream);
 
+/*
+ * helm_solve_static -- helm_solve for callers that cannot allocate device
+ * memory: code under HIP stream capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  Same arguments, kernels, results and report as
+ * helm_solve on the same plan, but the workspace of the solve is taken from a
+ * device array of HELM_STATIC_SCRATCH_BYTES bytes that the library holds on
+ * every GPU it runs on until the process ends, not from the plan's own
+ * workspace, and nothing is allocated (no hipMalloc, hipFree or host
+ * allocation: the plan builds every table it needs at setup).  The solve
+ * always runs eagerly with the refinement loop on the host (no captured
+ * graph; under a caller's stream capture only an unchecked FP64 solve can be
+ * recorded, since checking reads the residual norms on the host), and
+ * per-kernel profiling does not apply.
+ * Limits: nrhs <= HELM_STATIC_MAX_RHS, and the workspace of the solve (about
+ * three to four N x nrhs arrays of the plan's storage precision, plus
+ * boundary planes and partial sums) at most HELM_STATIC_SCRATCH_BYTES;
+ * larger solves return HELM_ENOMEM before any work is enqueued.
+ * Sharing: every call on one GPU uses that GPU's one array, which keeps the
+ * last call's contents (every kernel of a solve writes the workspace it later
+ * reads, so nothing needs clearing); calls that overlap in time on one GPU
+ * (two streams, two threads) race, and the caller must serialise them.
+ * The current device must be the plan's (else HELM_EINVAL).
+ * Errors: as helm_solve, and HELM_ENOMEM for sizes beyond the limits.
+ */
+#define HELM_STATIC_SCRATCH_BYTES (128u << 20)
+#define HELM_STATIC_MAX_RHS 1024
+int helm_solve_static(helm_plan* p, const void* f, void* u, int nrhs, void* stream);
+
 /* Report of the last helm_solve on this plan. */
 typedef struct helm_report {
     int    status;            /* status returned by the last solve */

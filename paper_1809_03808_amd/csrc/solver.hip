@@ -18,6 +18,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <cstdio>
 #include <cstdlib>
@@ -134,6 +135,13 @@ struct helm_plan {
   std::string tune_path;
   double tune_ms[2] = {-1.0, -1.0};  // measured FFT / dense solve times (AUTO)
   std::vector<double> h_norms;
+  // pinned host copy of the residual norms for solves that may not allocate
+  // ([2 * HELM_STATIC_MAX_RHS], allocated at setup)
+  double* h_norms_pin = nullptr;
+  // set while helm_solve_static runs: nothing may be allocated
+  bool no_alloc = false;
+  // this device's address of the static workspace array (helm_solve_static)
+  void* static_ws = nullptr;
   helm_report rep{};
   // per-kernel event timing
   struct Ev {
@@ -179,6 +187,7 @@ struct helm_plan {
     drop_graph();
     if (gcap) (void)hipStreamDestroy(gcap);
     if (ctl_host) (void)hipHostFree(ctl_host);
+    if (h_norms_pin) (void)hipHostFree(h_norms_pin);
     for (auto& e : evs) {
       (void)hipEventDestroy(e.a);
       (void)hipEventDestroy(e.b);
@@ -381,6 +390,7 @@ Roots* get_roots(helm_plan* p, int L, int sign) {
   auto& mp = sign < 0 ? p->roots_fwd : p->roots_inv;
   auto it = mp.find(L);
   if (it != mp.end()) return &it->second;
+  if (p->no_alloc) return nullptr;  // every table is built at setup (prepare_roots)
   Roots& r = mp[L];
   std::vector<double2> hd(L);
   std::vector<float2> hf(L);
@@ -408,6 +418,26 @@ void radix_plan(int L, FftPass& f) {
   if (rem == 2) f.radix[f.nst++] = 4;
   for (int i = 0; i < p / 3; ++i) f.radix[f.nst++] = 8;
   if (m9) f.radix[f.nst++] = 3, f.radix[f.nst++] = 3;
+}
+
+// Build every table of roots of unity the transforms of this plan use, so
+// that solves find them in place (and solves that may not allocate can run).
+int prepare_roots(helm_plan* p) {
+  for (int j = 0; j < p->nper; ++j) {
+    const PAxis& a = p->ax[j];
+    std::vector<int> lens;
+    if (!a.blue) {
+      lens = {a.n};
+      if (a.na > 1) lens.insert(lens.end(), {a.na, a.nbp});
+    } else {
+      lens = {a.M};
+      if (a.Mna > 1) lens.insert(lens.end(), {a.Mna, a.Mnbp});
+    }
+    for (int L : lens)
+      for (int sign : {-1, +1})
+        if (!get_roots(p, L, sign)) return HELM_ENOMEM;
+  }
+  return HELM_OK;
 }
 
 int pick_W(int L, int64_t, bool fp32) { return fft_tile_width(L, fp32); }
@@ -1099,10 +1129,63 @@ int64_t npoints(const helm_plan* p) {
   return n;
 }
 
+// Workspace buffers of a solve, in a fixed order (the order of
+// workspace_bytes and of the no-allocation layout).
+enum WsSlot { WS_W0, WS_W1, WS_W2, WS_R, WS_PART, WS_VB, WS_PIB, WS_P0, WS_P1, WS_P2, WS_P3, WS_SCR, WS_NORMS,
+              WS_BT1, WS_CTL, WS_N };
+
+std::array<DevMem*, WS_N> ws_bufs(helm_plan* p) {
+  return {&p->W0, &p->W1, &p->W2, &p->R, &p->part, &p->VB, &p->PIb, &p->P0,
+          &p->P1, &p->P2, &p->P3, &p->scratch, &p->norms, &p->BT1, &p->ctl};
+}
+
 // Addresses of every workspace buffer a captured solve refers to.
-std::array<void*, 15> workspace_addrs(const helm_plan* p) {
-  return {p->W0.p, p->W1.p, p->W2.p, p->R.p, p->part.p, p->VB.p, p->PIb.p, p->P0.p,
-          p->P1.p, p->P2.p, p->P3.p, p->scratch.p, p->norms.p, p->BT1.p, p->ctl.p};
+std::array<void*, WS_N> workspace_addrs(helm_plan* p) {
+  std::array<void*, WS_N> a;
+  const auto b = ws_bufs(p);
+  for (int i = 0; i < WS_N; ++i) a[i] = b[i]->p;
+  return a;
+}
+
+// Bytes of every workspace buffer a solve of nb right-hand sides needs (0:
+// not used by this plan).
+std::array<size_t, WS_N> workspace_bytes(const helm_plan* p, int nb, bool fp32, bool need_r) {
+  std::array<size_t, WS_N> w{};
+  const int64_t N = npoints(p);
+  const size_t esz = fp32 ? sizeof(float2) : sizeof(double2);
+  w[WS_W0] = (size_t)N * nb * esz;
+  w[WS_W1] = (size_t)N * nb * esz;
+  if (p->dim == 3 && (p->ax[0].na > 1 || p->ax[1].na > 1)) w[WS_W2] = (size_t)N * nb * esz;
+  if (need_r) w[WS_R] = (size_t)N * nb * esz;
+  // partial sums: max over the reductions used
+  size_t pe = 0;
+  if (p->dim == 2) {
+    pe = part_elems(1, nb, 1, p->ax[0].n, p->nL);
+  } else {
+    pe = std::max(part_elems(1, nb, p->ax[0].n, p->ax[1].n, p->nL),
+                  part_elems(2, nb, p->ax[0].n, p->ax[1].n, p->nL));
+  }
+  w[WS_PART] = pe * sizeof(double2);
+  const int64_t nO = p->dim == 2 ? 1 : p->ax[0].n;
+  w[WS_VB] = (size_t)nb * nO * 2 * p->nL * sizeof(double2);
+  w[WS_PIB] = w[WS_VB];
+  if (p->dim == 3) {
+    const size_t pl = (size_t)nb * 2 * p->ax[1].n * p->nL * sizeof(double2);
+    w[WS_P0] = w[WS_P1] = w[WS_P2] = w[WS_P3] = pl;
+  }
+  // Bluestein temporaries: the largest [O][M][S] of any transform that uses them
+  size_t tmax = 0;
+  if (p->dim == 2) {
+    if (p->ax[0].blue) tmax = (size_t)nb * p->ax[0].M * p->nL;
+  } else {
+    if (p->ax[0].blue) tmax = std::max(tmax, (size_t)nb * p->ax[0].M * p->ax[1].n * p->nL);
+    if (p->ax[1].blue) tmax = std::max(tmax, (size_t)nb * std::max(p->ax[0].n, 2) * p->ax[1].M * p->nL);
+  }
+  w[WS_BT1] = tmax * sizeof(double2);
+  w[WS_SCR] = (size_t)residual_scratch_len(p->dim, p->grid, nb) * sizeof(double);
+  w[WS_NORMS] = (size_t)nb * 2 * sizeof(double);
+  w[WS_CTL] = 64;
+  return w;
 }
 
 int ensure_workspace_impl(helm_plan* p, int nb, bool fp32, bool need_r);
@@ -1117,48 +1200,10 @@ int ensure_workspace(helm_plan* p, int nb, bool fp32, bool need_r) {
 }
 
 int ensure_workspace_impl(helm_plan* p, int nb, bool fp32, bool need_r) {
-  const int64_t N = npoints(p);
-  const size_t esz = fp32 ? sizeof(float2) : sizeof(double2);
-  HCHK(p->W0.ensure((size_t)N * nb * esz));
-  HCHK(p->W1.ensure((size_t)N * nb * esz));
-  bool need_w2 = false;
-  if (p->dim == 3) need_w2 = p->ax[0].na > 1 || p->ax[1].na > 1;
-  if (need_w2) HCHK(p->W2.ensure((size_t)N * nb * esz));
-  if (need_r) HCHK(p->R.ensure((size_t)N * nb * (fp32 ? sizeof(float2) : sizeof(double2))));
-  // partial sums: max over the reductions used
-  size_t pe = 0;
-  if (p->dim == 2) {
-    pe = part_elems(1, nb, 1, p->ax[0].n, p->nL);
-  } else {
-    pe = std::max(part_elems(1, nb, p->ax[0].n, p->ax[1].n, p->nL),
-                  part_elems(2, nb, p->ax[0].n, p->ax[1].n, p->nL));
-  }
-  HCHK(p->part.ensure(pe * sizeof(double2)));
-  const int64_t nO = p->dim == 2 ? 1 : p->ax[0].n;
-  HCHK(p->VB.ensure((size_t)nb * nO * 2 * p->nL * sizeof(double2)));
-  HCHK(p->PIb.ensure((size_t)nb * nO * 2 * p->nL * sizeof(double2)));
-  if (p->dim == 3) {
-    const size_t pl = (size_t)nb * 2 * p->ax[1].n * p->nL * sizeof(double2);
-    HCHK(p->P0.ensure(pl));
-    HCHK(p->P1.ensure(pl));
-    HCHK(p->P2.ensure(pl));
-    HCHK(p->P3.ensure(pl));
-  }
-  // Bluestein temporaries: the largest [O][M][S] of any transform that uses them
-  {
-    size_t tmax = 0;
-    if (p->dim == 2) {
-      if (p->ax[0].blue) tmax = (size_t)nb * p->ax[0].M * p->nL;
-    } else {
-      if (p->ax[0].blue) tmax = std::max(tmax, (size_t)nb * p->ax[0].M * p->ax[1].n * p->nL);
-      if (p->ax[1].blue)
-        tmax = std::max(tmax, (size_t)nb * std::max(p->ax[0].n, 2) * p->ax[1].M * p->nL);
-    }
-    if (tmax) HCHK(p->BT1.ensure(tmax * sizeof(double2)));
-  }
-  HCHK(p->scratch.ensure((size_t)residual_scratch_len(p->dim, p->grid, nb) * sizeof(double)));
-  HCHK(p->norms.ensure((size_t)nb * 2 * sizeof(double)));
-  HCHK(p->ctl.ensure(64));
+  const auto w = workspace_bytes(p, nb, fp32, need_r);
+  const auto b = ws_bufs(p);
+  for (int i = 0; i < WS_N; ++i)
+    if (w[i]) HCHK(b[i]->ensure(w[i]));
   p->h_norms.resize(2 * nb);
   return HELM_OK;
 }
@@ -1194,12 +1239,13 @@ int residual_norms(helm_plan* p, const double2* u, const double2* f, void* r, in
   a.r_kind = r_kind;
   HCHK(timed(p, K_RESID, (double)npoints(p) * nb * (2 * sizeof(double2) + (r ? esz_of(r_kind) : 0)), st,
              [&] { return launch_residual(a, st); }));
-  HCHK(hipMemcpyAsync(p->h_norms.data(), a.norms, nb * 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+  double* hn = p->no_alloc ? p->h_norms_pin : p->h_norms.data();
+  HCHK(hipMemcpyAsync(hn, a.norms, nb * 2 * sizeof(double), hipMemcpyDeviceToHost, st));
   HCHK(hipStreamSynchronize(st));
   double mx = 0.0;
   if (rel) rel->assign(nb, 0.0);
   for (int b = 0; b < nb; ++b) {
-    const double rr = p->h_norms[2 * b], ff = p->h_norms[2 * b + 1];
+    const double rr = hn[2 * b], ff = hn[2 * b + 1];
     if (!std::isfinite(rr) || !std::isfinite(ff)) {
       *relmax = NAN;
       return HELM_ENONFINITE;
@@ -1420,6 +1466,35 @@ int capture_solve(helm_plan* p, const double2* F, double2* U, int nb, hipStream_
   return HELM_OK;
 }
 
+// Refinement on the host: while the residual exceeds tol, solve for the
+// residual (stored in R by the last residual_norms) and add the correction
+// to u; stop at tol, at max_iter steps, or when a step fails to halve the
+// residual.  `it` steps were taken before, `rel` is the current residual.
+// Fills the plan's report and returns its status.
+int host_refine(helm_plan* p, const double2* F, double2* U, int nrhs, hipStream_t st, int it, double rel) {
+  const bool mixed = p->opt.precision == HELM_PREC_MIXED;
+  const int rk = mixed ? ST_C64 : ST_C128;
+  helm_report& rep = p->rep;
+  while (rel > p->opt.tol && it < p->opt.max_iter) {
+    int rc = solve_once(p, p->R.p, rk, U, 1, nrhs, mixed, st);
+    if (rc) return rep.status = rc;
+    ++it;
+    double nrel = 0;
+    rc = residual_norms(p, U, F, p->R.p, rk, nrhs, st, &nrel, nullptr);
+    rep.iterations = it;
+    rep.rel_residual_max = nrel;
+    if (rc) return rep.status = rc;
+    if (!(nrel < 0.5 * rel)) {
+      rel = nrel;
+      break;  // stagnation
+    }
+    rel = nrel;
+  }
+  rep.iterations = it;
+  rep.status = rel <= p->opt.tol ? HELM_OK : HELM_ENOCONV;
+  return rep.status;
+}
+
 // helm_solve.  The first call with given arguments runs eagerly with the
 // refinement loop on the host; a repeat of the same arguments (pointers,
 // count, stream) captures the solve with as many device-controlled
@@ -1498,24 +1573,115 @@ int solve_entry(helm_plan* p, const void* f, void* u, int nrhs, hipStream_t st, 
     rep.rel_residual_max = rel;
     if (rc) return rep.status = rc;
   }
-  while (rel > p->opt.tol && it < p->opt.max_iter) {
-    rc = solve_once(p, p->R.p, rk, U, 1, nrhs, mixed, st);
-    if (rc) return rep.status = rc;
-    ++it;
-    double nrel = 0;
-    rc = residual_norms(p, U, F, p->R.p, rk, nrhs, st, &nrel, nullptr);
-    rep.iterations = it;
-    rep.rel_residual_max = nrel;
-    if (rc) return rep.status = rc;
-    if (!(nrel < 0.5 * rel)) {
-      rel = nrel;
-      break;  // stagnation
+  rc = host_refine(p, F, U, nrhs, st, it, rel);
+  if (rc == HELM_OK || rc == HELM_ENOCONV) p->prev_steps = p->rep.iterations;
+  return rc;
+}
+
+}  // namespace
+
+}  // namespace helm
+
+// ---------------------------------------------------------------------------
+// Solves that allocate nothing (helm_solve_static).  Their workspace is this
+// file-scope device array: every GPU the library runs on holds its own copy
+// until the process ends.  In host code the name `scratch` is only a host-side
+// stand-in; the device address is obtained once per device with
+// hipGetSymbolAddress (static_workspace) and only that address is used.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[HELM_STATIC_SCRATCH_BYTES];
+
+namespace helm {
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// This device's address of `scratch` (the device must be current).
+int static_workspace(int dev, void** out) {
+  if (dev < 0 || dev >= kMaxDevices) return HELM_EUNSUPPORTED;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+      (void)hipGetLastError();
+      return HELM_EDEVICE;
     }
-    rel = nrel;
+    g_scratch_ptr[dev] = ptr;
   }
-  p->prev_steps = it;
-  rep.status = rel <= p->opt.tol ? HELM_OK : HELM_ENOCONV;
-  return rep.status;
+  *out = g_scratch_ptr[dev];
+  return HELM_OK;
+}
+
+size_t round256(size_t b) { return (b + 255) / 256 * 256; }
+
+// The plan's workspace buffers pointed into the static array for the scope
+// of one solve, then restored (the plan's own buffers and captured graphs
+// are untouched).
+struct StaticWorkspace {
+  helm_plan* p;
+  std::array<std::pair<void*, size_t>, WS_N> saved;
+  bool prof;
+  StaticWorkspace(helm_plan* pl, const std::array<size_t, WS_N>& w) : p(pl) {
+    const auto b = ws_bufs(p);
+    char* base = static_cast<char*>(p->static_ws);
+    size_t off = 0;
+    for (int i = 0; i < WS_N; ++i) {
+      saved[i] = {b[i]->p, b[i]->bytes};
+      b[i]->p = w[i] ? base + off : nullptr;
+      b[i]->bytes = w[i];
+      off += round256(w[i]);
+    }
+    prof = p->prof;
+    p->prof = false;  // per-kernel events would be created on first use
+    p->no_alloc = true;
+    p->skip_cur = nullptr;
+  }
+  ~StaticWorkspace() {
+    const auto b = ws_bufs(p);
+    for (int i = 0; i < WS_N; ++i) {
+      b[i]->p = saved[i].first;
+      b[i]->bytes = saved[i].second;
+    }
+    p->prof = prof;
+    p->no_alloc = false;
+  }
+};
+
+int solve_static(helm_plan* p, const void* f, void* u, int nrhs, hipStream_t st) {
+  if (!p || !f || !u || nrhs < 1 || f == u) return HELM_EINVAL;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return HELM_EDEVICE;
+  if (dev != p->device || !p->static_ws || !p->h_norms_pin) return HELM_EINVAL;
+  const bool mixed = p->opt.precision == HELM_PREC_MIXED;
+  const bool check = mixed || p->opt.check;
+  helm_report& rep = p->rep;
+  rep = helm_report{};
+  rep.precision = p->opt.precision;
+  rep.transform = p->dense ? HELM_TRANSFORM_DENSE : HELM_TRANSFORM_FFT;
+  rep.nrhs = nrhs;
+  rep.rel_residual_max = -1;
+  rep.rel_residual_first = -1;
+  if (nrhs > HELM_STATIC_MAX_RHS) return rep.status = HELM_ENOMEM;
+  const auto w = workspace_bytes(p, nrhs, mixed, check);
+  size_t total = 0;
+  for (size_t b : w) total += round256(b);
+  if (total > (size_t)HELM_STATIC_SCRATCH_BYTES) return rep.status = HELM_ENOMEM;
+  StaticWorkspace ws(p, w);
+  const double2* F = reinterpret_cast<const double2*>(f);
+  double2* U = reinterpret_cast<double2*>(u);
+  int rc = solve_once(p, f, ST_C128, U, 0, nrhs, mixed, st);
+  if (rc) return rep.status = rc;
+  if (!check) return rep.status = HELM_OK;
+  double rel = 0;
+  rc = residual_norms(p, U, F, p->R.p, mixed ? ST_C64 : ST_C128, nrhs, st, &rel, nullptr);
+  rep.rel_residual_first = rel;
+  rep.rel_residual_max = rel;
+  if (rc) return rep.status = rc;
+  return host_refine(p, F, U, nrhs, st, 0, rel);
 }
 
 }  // namespace
@@ -1817,6 +1983,16 @@ int helm_setup(int dim, const int64_t* grid, const double* h, double omega, uint
     }
     if (hipDeviceSynchronize() != hipSuccess) return HELM_EDEVICE;
   }
+  if (prepare_roots(p.get()) != HELM_OK) return HELM_ENOMEM;
+  if (hipHostMalloc(reinterpret_cast<void**>(&p->h_norms_pin), 2 * HELM_STATIC_MAX_RHS * sizeof(double),
+                    hipHostMallocDefault) != hipSuccess) {
+    p->h_norms_pin = nullptr;
+    return HELM_ENOMEM;
+  }
+  {
+    const int src = static_workspace(p->device, &p->static_ws);
+    if (src != HELM_OK) return src;
+  }
   if (tf == HELM_TRANSFORM_DENSE) {
     p->dense = 1;
   } else if (tf == HELM_TRANSFORM_AUTO && dense_ok) {
@@ -1832,6 +2008,10 @@ int helm_setup(int dim, const int64_t* grid, const double* h, double omega, uint
 
 int helm_solve(helm_plan* p, const void* f, void* u, int nrhs, void* stream) {
   return helm::solve_entry(p, f, u, nrhs, reinterpret_cast<hipStream_t>(stream), true);
+}
+
+int helm_solve_static(helm_plan* p, const void* f, void* u, int nrhs, void* stream) {
+  return helm::solve_static(p, f, u, nrhs, reinterpret_cast<hipStream_t>(stream));
 }
 
 int helm_report_get(const helm_plan* p, helm_report* out) {

@@ -36,7 +36,11 @@ EXPORTS = (
     "helm_residual", "helm_destroy", "helm_strerror", "helm_eig1d",
     "helm_profile", "helm_kernel_stats_get", "helm_kernel_name",
     "helm_batch_create", "helm_batch_solve", "helm_batch_report_get", "helm_batch_destroy",
+    "helm_solve_static",
 )
+
+STATIC_SCRATCH_BYTES = 128 << 20
+STATIC_MAX_RHS = 1024
 
 NKERNELS = 8
 
@@ -85,6 +89,8 @@ def lib():
     L.helm_setup.restype = ctypes.c_int
     L.helm_solve.argtypes = [vp, vp, vp, ctypes.c_int, vp]
     L.helm_solve.restype = ctypes.c_int
+    L.helm_solve_static.argtypes = [vp, vp, vp, ctypes.c_int, vp]
+    L.helm_solve_static.restype = ctypes.c_int
     L.helm_report_get.argtypes = [vp, ctypes.POINTER(Report)]
     L.helm_report_get.restype = ctypes.c_int
     L.helm_residual.argtypes = [vp, vp, vp, vp, dp, ctypes.c_int, vp]
@@ -200,6 +206,18 @@ class Plan:
                               nrhs, _stream_ptr(stream))
         if rc != HELM_OK and raise_on_error:
             raise HelmError(rc, "helm_solve")
+        return rc
+
+    def solve_static(self, f, u, stream=None, raise_on_error=True):
+        """helm_solve_static: the same solve with the library's static device
+        workspace (nothing allocated).  Returns the status."""
+        nrhs = _check_tensor(f, self.grid, "f")
+        if _check_tensor(u, self.grid, "u") != nrhs:
+            raise ValueError("f and u hold different numbers of right-hand sides")
+        rc = lib().helm_solve_static(self._p, ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(u.data_ptr()),
+                                     nrhs, _stream_ptr(stream))
+        if rc != HELM_OK and raise_on_error:
+            raise HelmError(rc, "helm_solve_static")
         return rc
 
     def report(self):
