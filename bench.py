@@ -27,8 +27,9 @@ The line also carries
                    side of the workload: the dense separation-of-variables
                    solve (eqs. (A2Dinv), (A3Dinv)) and the FP64 residual, with
                    the error of the GPU result against that reference;
-  extra         -- the 2D 4096^2 and 3D 256^3 workloads and the 64-problem
-                   uneven batch (unless --no-extra).
+  extra         -- the 2D 4096^2 and 3D 256^3 workloads, the 64-problem
+                   uneven batch and the paper's own shapes (omega = 2 pi, its
+                   load; Tables 1-4) (unless --no-extra).
 
 Algorithmic bytes per unknown (N-sized arrays read or written once; element
 e = 16 B for complex128 and 8 B for complex64 storage; a transform counts one
@@ -54,6 +55,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# the paper's "fast solver" column (Section 6, Tables 1-4; MATLAB on an Intel
+# i5-6267U laptop), seconds, for the shapes it reports
+PAPER_FAST_SOLVER_S = {"paper_2d_2049": 4.58, "paper_3d_513": 672.27, "paper_2d_65x2049": 0.10,
+                       "paper_2d_2049x65": 0.12, "paper_3d_9x513x513": 10.95, "paper_3d_513x9x513": 8.00,
+                       "paper_3d_513x513x9": 7.01}
 METRIC = "solved unknowns/s at rel. residual ≤1e-10, FP32+refine vs FP64; % HBM peak"
 
 
@@ -421,6 +427,8 @@ def main():
                     help="skip per-kernel event timing (pure wall-clock run)")
     ap.add_argument("--only", choices=["fp64", "mixed"], default=None,
                     help="profiling aid: run one leg of the workload only, no extras, no JSON roofline")
+    ap.add_argument("--transform", choices=["fft", "dense"], default="fft",
+                    help="with --only: the periodised-axis transform of the plan")
     ap.add_argument("--copy-calibration-gib", type=float, default=0.0,
                     help="after the run, copy a buffer of this size (for counter calibration)")
     args = ap.parse_args()
@@ -449,7 +457,8 @@ def main():
         f = inputs.gaussian_device(grid, [inputs.rhs_seed(wl["config"], 0, r) for r in range(wl["nrhs"])], "cuda")
         u = torch.empty_like(f)
         prec = helm.PREC_FP64 if args.only == "fp64" else helm.PREC_MIXED
-        plan = helm.Plan(grid, inputs.spacing(grid), wl["omega"], precision=prec, check=True)
+        tf = helm.TRANSFORM_DENSE if args.transform == "dense" else helm.TRANSFORM_FFT
+        plan = helm.Plan(grid, inputs.spacing(grid), wl["omega"], precision=prec, check=True, transform=tf)
         ms, rep = _time_steps(plan, f, u, args.steps, args.warmup)
         _log(f"{args.workload} {args.only}: {ms:.3f} ms/step report {rep}")
         if not args.no_profile:
@@ -465,7 +474,8 @@ def main():
             b.copy_(a)
             torch.cuda.synchronize()
             _log(f"copy calibration: {nbytes} bytes read, {nbytes} bytes written")
-        print(json.dumps({"workload": args.workload, "leg": args.only, "ms_per_step": ms, "report": rep}))
+        print(json.dumps({"workload": args.workload, "leg": args.only, "transform": args.transform,
+                          "ms_per_step": ms, "report": rep}))
         return
 
     head = run_workload(args.workload, args.steps, args.warmup, profile=not args.no_profile,
@@ -478,6 +488,13 @@ def main():
                 extra[name] = run_workload(name, max(args.steps, 10), args.warmup, profile=not args.no_profile)
         extra["2d_batch64"] = batch_leg(max(3, args.steps // 4), 1)
         _log("batch", extra["2d_batch64"])
+        # the paper's own shapes (omega = 2 pi, its load), with its MATLAB
+        # fast-solver times on a laptop CPU as context (not a target)
+        from paper_1809_03808_amd import inputs
+        for name in inputs.PAPER_SHAPED:
+            d = run_workload(name, 5, 2, profile=False)
+            d["paper_fast_solver_s_laptop_matlab"] = PAPER_FAST_SOLVER_S.get(name)
+            extra[name] = d
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(args.workload, f0, u0)

@@ -212,6 +212,37 @@ def rel_residual(grid, h, omega, abc, u, f):
     return np.linalg.norm(np.atleast_2d(r), axis=-1) / np.linalg.norm(np.atleast_2d(f), axis=-1)
 
 
+def norm_bound(grid, h, omega, abc):
+    """Upper bound of ||A||_2 from the Kronecker form of eqs. (A2D), (A3D):
+    A is symmetric, so ||A||_2 <= ||A||_inf, and the triangle inequality with
+    ||X (x) Y||_inf = ||X||_inf ||Y||_inf bounds ||A||_inf by the sum over the
+    terms of the products of the 1D factors' row-sum norms."""
+    d = len(grid)
+    K = [stiffness_1d(grid[j], h[j], omega, abc[j][0], abc[j][1]) for j in range(d)]
+    M = [mass_1d(grid[j], h[j]) for j in range(d)]
+    ni = lambda X: float(np.max(np.sum(np.abs(X), axis=1)))  # noqa: E731
+    S1 = ni(K[0] - omega ** 2 * M[0])
+    nK = [ni(x) for x in K]
+    nM = [ni(x) for x in M]
+    if d == 2:
+        return S1 * nM[1] + nM[0] * nK[1]
+    return S1 * nM[1] * nM[2] + nM[0] * nK[1] * nM[2] + nM[0] * nM[1] * nK[2]
+
+
+def backward_error(grid, h, omega, abc, u, f):
+    """Normwise backward error ||f - A u|| / (||A|| ||u|| + ||f||) per right-hand
+    side (2-norms, ||A|| from ``norm_bound``): the size of the smallest
+    relative perturbation of A and f of which u is the exact solution, up to
+    the bound on ||A||.  A backward-stable direct solve makes it a small
+    multiple of the unit roundoff whatever the conditioning, whereas the
+    relative residual ||f - A u|| / ||f|| also grows with ||A|| ||u|| / ||f||."""
+    r = np.atleast_2d(residual(grid, h, omega, abc, u, f))
+    u = np.atleast_2d(u)
+    f = np.atleast_2d(f)
+    nA = norm_bound(grid, h, omega, abc)
+    return np.linalg.norm(r, axis=-1) / (nA * np.linalg.norm(u, axis=-1) + np.linalg.norm(f, axis=-1))
+
+
 def rel_error(u, u_ref):
     """Per right-hand side ||u - u_ref||_2 / ||u_ref||_2."""
     u = np.atleast_2d(u)

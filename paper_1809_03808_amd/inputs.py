@@ -111,7 +111,21 @@ def workload(name):
         return dict(dim=2, grid=(2049, 2049), omega=TWO_PI, nrhs=1, config=6, rhs="paper")
     if name == "paper_3d_513":
         return dict(dim=3, grid=(513, 513, 513), omega=TWO_PI, nrhs=1, config=7, rhs="paper")
+    # the anisotropic shapes of the paper's Tables 2 and 4 (same omega and load)
+    if name in PAPER_ANISOTROPIC:
+        grid = PAPER_ANISOTROPIC[name]
+        return dict(dim=len(grid), grid=grid, omega=TWO_PI, nrhs=1, config=8, rhs="paper")
     raise KeyError(name)
+
+
+PAPER_ANISOTROPIC = {
+    "paper_2d_65x2049": (65, 2049),
+    "paper_2d_2049x65": (2049, 65),
+    "paper_3d_9x513x513": (9, 513, 513),
+    "paper_3d_513x9x513": (513, 9, 513),
+    "paper_3d_513x513x9": (513, 513, 9),
+}
+PAPER_SHAPED = ("paper_2d_2049", "paper_3d_513") + tuple(PAPER_ANISOTROPIC)
 
 
 def batched_2d_problems(count=64, seed=4000):

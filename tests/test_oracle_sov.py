@@ -119,3 +119,41 @@ def test_sov_long_axis_uses_reduction_and_matches_banded_lu():
     ub = fem.solve(grid, h, w, abc, f)
     us = sov.solve(grid, h, w, abc, f, refine=1)
     assert np.linalg.norm(us - ub) <= 1e-12 * np.linalg.norm(ub)
+
+
+def test_sov_refined_near_resonance_matches_banded_lu():
+    """omega = 2 pi on a long axis with the paper's load (the paper's
+    experiments): refined to a backward error at rounding level, the result
+    equals banded LU to within the problem's conditioning."""
+    grid = (1025, 9)
+    h = inputs.spacing(grid)
+    abc = _abc(2, 0b1111)
+    f = inputs.paper_rhs(grid).reshape(-1)
+    ub = fem.solve(grid, h, 2 * np.pi, abc, f)
+    us, eta, steps = sov.solve_refined(grid, h, 2 * np.pi, abc, f)
+    assert eta <= 1e-15
+    assert abs(fem.backward_error(grid, h, 2 * np.pi, abc, us[None], f[None])[0] - eta) <= 1e-17
+    assert np.linalg.norm(us - ub) <= 1e-10 * np.linalg.norm(ub)
+
+
+@pytest.mark.parametrize("grid,mask,omega", [((9, 7), 0b1111, 5.0), ((6, 5, 4), 0b110111, 4.0),
+                                             ((17, 12), 0b0110, 2 * np.pi)])
+def test_norm_bound_and_backward_error(grid, mask, omega):
+    """norm_bound bounds the exact ||A||_inf (and ||A||_2) from above within a
+    small factor; banded LU has a backward error at rounding level, and a
+    relative perturbation of size e of its solution one of order e."""
+    import scipy.sparse.linalg as spl
+    h = inputs.spacing(grid)
+    abc = _abc(len(grid), mask)
+    A = fem.operator(grid, h, omega, abc)
+    nb = fem.norm_bound(grid, h, omega, abc)
+    ninf = spl.norm(A, np.inf)
+    n2 = np.linalg.norm(A.toarray(), 2)
+    assert ninf <= nb * (1 + 1e-14) and n2 <= nb * (1 + 1e-14) and nb <= 4 * ninf
+    f = inputs.gaussian(grid, 5).reshape(-1)
+    u = fem.solve(grid, h, omega, abc, f)
+    assert fem.backward_error(grid, h, omega, abc, u[None], f[None])[0] <= 1e-15
+    rng = np.random.default_rng(6)
+    up = u * (1 + 1e-9 * rng.standard_normal(u.size))
+    eta = fem.backward_error(grid, h, omega, abc, up[None], f[None])[0]
+    assert 1e-12 <= eta <= 1e-8
