@@ -56,7 +56,8 @@ extern "C" {
                                FP64 solution update (iterative refinement) */
 
 /* Solver options.  helm_default_options fills: precision = HELM_PREC_FP64,
- * tol = 1e-10, max_iter = 8, check = 1. */
+ * tol = 1e-10, max_iter = 8, check = 1, transform = FFT, tune_cache = NULL,
+ * boundary = AUTO. */
 /* Transform along the periodised axes (helm_options.transform):
  *   FFT   the fast method of Sections 4.2 / 5.2: DFTs of the periodic
  *         problem, three line passes and the boundary steps;
@@ -72,6 +73,28 @@ extern "C" {
 #define HELM_TRANSFORM_DENSE 2
 #define HELM_DENSE_MAX 1024
 
+/* Evaluation of the boundary steps in 3D (helm_options.boundary; 2D always
+ * uses line sweeps).  Step 2 of the method (eqs. (step2-1)-(step2-3)) maps two
+ * boundary vectors to w_k = sum_k' sum_j V^b[k,j] V^b[k',j] T_j^{-1} r_k', a
+ * linear map that depends on the operator only:
+ *   LINES   sweep the N/n_3 line systems for it in every solve (the inner
+ *           Step 2 of the outer Steps 1 and 3, and the whole outer Step 2);
+ *   TABLES  build that map once at setup as dense n_3 x n_3 blocks (per outer
+ *           mode for the inner Step 2, per inner absorbing mode for the outer
+ *           Step 2, the latter after the dense inner eigenvector transform of
+ *           the two boundary planes) and apply it as a batched matrix product:
+ *           5 of the 9 line sweeps of a 3D solve become products with
+ *           64 n_3^2 (n_1 + n_2) bytes of tables;
+ *   AUTO    build the tables when they fit the memory budget (at most 32 GiB
+ *           and a quarter of the free device memory) and use them for solves
+ *           of at least as many right-hand sides as the plan measured them to
+ *           pay for (timed at setup with 1 and 16 right-hand sides; cached in
+ *           tune_cache when set).
+ * Both give A^{-1} f up to rounding. */
+#define HELM_BOUNDARY_AUTO   0
+#define HELM_BOUNDARY_LINES  1
+#define HELM_BOUNDARY_TABLES 2
+
 typedef struct helm_options {
     int    precision; /* HELM_PREC_FP64 or HELM_PREC_MIXED */
     double tol;       /* target ||f - A u||_2 / ||f||_2 per right-hand side */
@@ -81,6 +104,7 @@ typedef struct helm_options {
                          The mixed path always checks. */
     int    transform; /* HELM_TRANSFORM_*; default FFT */
     const char* tune_cache; /* AUTO only: decision cache file, or NULL */
+    int    boundary;  /* HELM_BOUNDARY_*; default AUTO */
 } helm_options;
 
 void helm_default_options(helm_options* opt);
@@ -175,6 +199,7 @@ typedef struct helm_report {
     double rel_residual_max;  /* max over RHS of ||f - A u|| / ||f|| (FP64), -1 if unchecked */
     double rel_residual_first;/* same after the first solve, -1 if unchecked */
     int    transform;         /* HELM_TRANSFORM_FFT or _DENSE: the variant the plan runs */
+    int    boundary;          /* HELM_BOUNDARY_LINES or _TABLES: how the boundary steps ran */
 } helm_report;
 
 int helm_report_get(const helm_plan* p, helm_report* out);
@@ -198,9 +223,10 @@ int helm_residual(helm_plan* p, const void* u, const void* f, void* r,
  * the summed algorithmic bytes (the N-sized arrays each launch must read and
  * write once: 2 x element size per unknown for a transform pass, 1x, 0x or 2x
  * for the Step 1 / Step 2 / Step 3 line solves, 32 bytes for the FP64
- * residual).  reset != 0 clears the accumulators afterwards.
+ * residual; the table bytes for the boundary-table products).  reset != 0
+ * clears the accumulators afterwards.
  */
-#define HELM_NKERNELS 8
+#define HELM_NKERNELS 9
 typedef struct helm_kernel_stats {
     double ms[HELM_NKERNELS];
     double bytes[HELM_NKERNELS];

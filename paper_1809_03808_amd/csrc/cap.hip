@@ -1,0 +1,119 @@
+// Boundary operators applied from precomputed tables.
+//
+// The boundary step of the three-step method (Step 2, eqs. (step2-1)-(step2-3))
+// maps the two boundary vectors r_0, r_1 of a group of line systems to
+//   w_k = sum_{k'} sum_j  V^b[k, j] V^b[k', j] T_j^{-1} r_{k'},
+// a sum over the modes j of the other periodised direction of the inverses
+// of that group's tridiagonal line matrices T_j.  The map depends on the
+// operator only, so the plan evaluates it once as dense nL x nL blocks (one
+// column per unit right-hand side, through the line solver), and every solve
+// applies it as a batched complex matrix product instead of sweeping all
+// N/nL lines again.  In 3D this replaces the Step-2 line sweep of every inner
+// solve (groups = outer modes l, sum over the inner modes m) and the whole
+// outer Step 2 (groups = inner absorbing modes m after the inner
+// eigenvector transform, sum over the outer modes l).
+//
+// Kernel: blocks of 256 threads per (group, output rows (k, x)); each lane
+// accumulates a 4-row x 4-right-hand-side tile in registers while streaming
+// its rows of the table, which is read from memory once per launch for up to
+// 16 right-hand sides (the waves of a block that share rows take different
+// right-hand sides).  The table is symmetric (T_j^{-1} is complex
+// symmetric), so row r of the product reads column r of the stored blocks:
+// consecutive lanes read consecutive addresses.  The input vectors are the
+// same for every lane of a wave, so their loads are uniform (scalar) loads.
+#include "helm_internal.h"
+
+namespace helm {
+
+namespace {
+
+constexpr int kCapThreads = 256;
+
+// Register tile: each lane computes 4 rows (r0 + lane + 64 i) times TN
+// right-hand sides; RG waves of a block share its rows and take consecutive
+// groups of TN right-hand sides, so a block covers 256 * 4 / RG rows and
+// RG * TN right-hand sides per pass over the table.
+template <int TN, int RG>
+__global__ __launch_bounds__(kCapThreads) void cap_apply_kernel(const double2* __restrict__ T0,
+                                                                const double2* __restrict__ T1,
+                                                                const double2* __restrict__ in,
+                                                                double2* __restrict__ out, CapArgs a) {
+  constexpr int TM = 4;
+  constexpr int RPB = 64 * TM * (4 / RG);  // rows per block
+  if (a.skip && *a.skip) return;
+  const int nL = a.nL, rows = 2 * nL;
+  const int rt = (rows + RPB - 1) / RPB;
+  const int g = (int)(blockIdx.x / rt);
+  const int wv = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+  const int rg = wv % RG;
+  const int rbase = (int)(blockIdx.x % rt) * RPB + (wv / RG) * 64 * TM + ((int)threadIdx.x & 63);
+  const int64_t ts = (int64_t)a.G * rows;  // stride between x' rows of a table
+  for (int b0 = rg * TN; b0 < a.nb; b0 += RG * TN) {
+    double2 acc[TM][TN];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int j = 0; j < TN; ++j) acc[i][j] = make_double2(0, 0);
+    for (int kp = 0; kp < 2; ++kp) {
+      const double2* T = (kp ? T1 : T0) + (int64_t)g * rows;
+      // uniform (scalar) pointers to this wave's right-hand sides; those past
+      // nb repeat the last one and their products are dropped
+      const double2* X[TN];
+#pragma unroll
+      for (int j = 0; j < TN; ++j)
+        X[j] = in + (int64_t)(b0 + j < a.nb ? b0 + j : a.nb - 1) * a.in_b + (int64_t)g * a.in_g + kp * a.in_k;
+      int ro[TM];
+#pragma unroll
+      for (int i = 0; i < TM; ++i) ro[i] = min(rbase + 64 * i, rows - 1);
+#pragma unroll 2
+      for (int xp = 0; xp < nL; ++xp) {
+        double2 t[TM];
+#pragma unroll
+        for (int i = 0; i < TM; ++i) t[i] = T[(int64_t)xp * ts + ro[i]];
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+          const double2 v = X[j][xp];
+#pragma unroll
+          for (int i = 0; i < TM; ++i) acc[i][j] = cfma(t[i], v, acc[i][j]);
+        }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < TM; ++i) {
+      const int r = rbase + 64 * i;
+      if (r < rows) {
+        const int k = r >= nL ? 1 : 0, x = r - k * nL;
+        double2* o = out + (int64_t)g * a.out_g + k * a.out_k + x;
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+          if (b0 + j < a.nb) o[(int64_t)(b0 + j) * a.out_b] = acc[i][j];
+      }
+    }
+  }
+}
+
+template <int TN, int RG>
+hipError_t launch_nbc(const CapArgs& a, hipStream_t s) {
+  constexpr int RPB = 64 * 4 * (4 / RG);
+  const int64_t blocks = (int64_t)a.G * ((2 * a.nL + RPB - 1) / RPB);
+  if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((cap_apply_kernel<TN, RG>), dim3((unsigned)blocks), dim3(kCapThreads), 0, s, a.T0, a.T1,
+                     a.in, a.out, a);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_cap_apply(const CapArgs& a, hipStream_t s) {
+  if (a.nb < 1 || a.G < 1 || a.nL < 1 || !a.T0 || !a.T1 || !a.in || !a.out) return hipErrorInvalidValue;
+  // TN right-hand sides per wave (the smallest power of two covering nb, at
+  // most 4) and RG waves sharing rows: up to 16 right-hand sides per pass
+  // over the table, more in further passes
+  if (a.nb <= 1) return launch_nbc<1, 1>(a, s);
+  if (a.nb <= 2) return launch_nbc<2, 1>(a, s);
+  if (a.nb <= 4) return launch_nbc<4, 1>(a, s);
+  if (a.nb <= 8) return launch_nbc<4, 2>(a, s);
+  return launch_nbc<4, 4>(a, s);
+}
+
+}  // namespace helm

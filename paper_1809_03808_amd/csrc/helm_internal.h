@@ -169,6 +169,10 @@ struct LineArgs {
   int tile = 0;    // lines per workgroup tile
   int ntiles = 0;  // tiles along the reduced (or flattened) index
   const int* skip = nullptr;     // device flag: the launch does nothing while *skip != 0
+  // Unit right-hand sides (plan setup only): with no `in`, line (b, l, m) has
+  // the right-hand side e_b (b < nL), so that reductions of the solutions
+  // assemble columns of reduced inverses (the boundary operator tables).
+  int unit_rhs = 0;
 };
 
 hipError_t launch_lines(LineArgs a, hipStream_t s);
@@ -179,6 +183,26 @@ void lines_geometry(int nL, int* P, int* c, int* NT);
 // reciprocal Thomas pivot entering the chunk of lane q (P, c from
 // lines_geometry; entry q = 0 is zero).  Computed once per plan.
 hipError_t launch_line_factors(const LineArgs& a, double2* piv, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// Boundary operator tables (cap.hip): for every group g < G (an outer or an
+// inner mode), the reduced inverse of that group's line matrices acting on
+// two boundary vectors,
+//   out[b][g][k][x] = sum_{k' < 2} sum_{x' < nL} T_{k'}[x'][g][k][x] in[b][g][k'][x'],
+// with T_{k'} stored [nL (x')][G][2 (k)][nL (x)] and the vectors addressed by
+// b * _b + g * _g + k * _k + x strides.
+// ---------------------------------------------------------------------------
+struct CapArgs {
+  int nb = 0, G = 0, nL = 0;
+  const double2* T0 = nullptr;
+  const double2* T1 = nullptr;
+  const double2* in = nullptr;
+  int64_t in_b = 0, in_g = 0, in_k = 0;
+  double2* out = nullptr;
+  int64_t out_b = 0, out_g = 0, out_k = 0;
+  const int* skip = nullptr;
+};
+hipError_t launch_cap_apply(const CapArgs& a, hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // Dense eigenvector transforms on the matrix cores (dense.hip)

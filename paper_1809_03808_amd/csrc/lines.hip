@@ -266,6 +266,7 @@ struct LineDev {
   void* out;
   double2* part;
   const int* skip;
+  int unit_rhs;
 };
 
 struct RowCoef {
@@ -521,8 +522,9 @@ __global__ __launch_bounds__(NT) void lines_kernel(LineDev a) {
       } else {
 #pragma unroll
         for (int jj = 0; jj < kCMax; ++jj) {
-          const int r = jj * 64 + lane;
-          if (r < seg) S[stage_pos(si * seg + r)] = make_double2(0, 0);
+          const int r = jj * 64 + lane, x = wx0 + r;
+          const bool one = a.unit_rhs && sv && x == (int)sb;
+          if (r < seg) S[stage_pos(si * seg + r)] = make_double2(one ? 1.0 : 0.0, 0);
         }
       }
       // Rank-2 terms.  Kernels of exact lines load the rows of a source in
@@ -617,6 +619,7 @@ __global__ __launch_bounds__(NT) void lines_kernel(LineDev a) {
     if (XR && last && valid) {
       const int x = nL - 1;
       if (a.in) xrhs = to_d2(reinterpret_cast<const T*>(a.in)[loff + x]);
+      else if (a.unit_rhs && (int)b == x) xrhs = make_double2(1, 0);
       if (a.PO) {
         const double2* po = a.PO + (int64_t)(b * 2) * a.nI * nL + (int64_t)m * nL;
         xrhs = cfma(a.alpha0[l], po[x], xrhs);
@@ -918,6 +921,7 @@ LineDev make_dev(const LineArgs& a, int P, int c) {
   d.sTab = a.sTab;
   d.out = a.out; d.part = a.part;
   d.skip = a.skip;
+  d.unit_rhs = a.unit_rhs;
   d.tile = d.ntiles = d.iters = 0;
   (void)P;
   return d;

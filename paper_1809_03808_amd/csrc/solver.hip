@@ -132,6 +132,15 @@ struct helm_plan {
   // device-side refinement control (IrCtl) for captured solves
   helm::DevMem ctl;
   int dense = 0;  // 1: periodised axes use the dense eigenvector transforms
+  // Boundary operator tables (3D, helm_options.boundary): capW holds the
+  // inner Step-2 map of every outer periodic mode l (line family (B, A)),
+  // capH the outer Step-2 map of every inner absorbing mode m (family
+  // (A, A)); each as two blocks T_{k'}[x'][g][k][x] (cap.hip).  Solves of at
+  // least cap_min_nb right-hand sides use them (0: never).
+  helm::DevMem capW, capH;
+  const double2 *capW0 = nullptr, *capW1 = nullptr, *capH0 = nullptr, *capH1 = nullptr;
+  int cap_min_nb = 0;
+  double cap_ms[4] = {-1, -1, -1, -1};  // measured: lines at 1 and 16 RHS, tables at 1 and 16 RHS
   std::string tune_path;
   double tune_ms[2] = {-1.0, -1.0};  // measured FFT / dense solve times (AUTO)
   std::vector<double> h_norms;
@@ -217,7 +226,8 @@ int map_err(hipError_t e) {
 
 // Kernel slots of helm_kernel_stats.
 enum KSlot {
-  K_FFT64 = 0, K_FFT32 = 1, K_LINES = 2, K_INNER_MID = 3, K_SUM = 4, K_OUTER_MID = 5, K_RESID = 6, K_DENSE = 7
+  K_FFT64 = 0, K_FFT32 = 1, K_LINES = 2, K_INNER_MID = 3, K_SUM = 4, K_OUTER_MID = 5, K_RESID = 6, K_DENSE = 7,
+  K_CAP = 8
 };
 
 // Launch through `fn` (returning hipError_t), bracketed by events if profiling.
@@ -771,7 +781,33 @@ struct InnerIO {
   const double2* seedA = nullptr;  // line matrices with the absorbing inner branch (S2)
   const double2* sigTB = nullptr;  // their sigma tables
   const double2* sigTA = nullptr;
+  bool capS2 = false;  // Step 2 from the plan's table capW instead of a line sweep
 };
+
+// Product of a boundary operator table with nb pairs of boundary vectors
+// (cap.hip), timed with the table bytes it streams.
+int cap_apply(helm_plan* p, const double2* T0, const double2* T1, int nb, int G, const double2* in,
+              int64_t in_b, int64_t in_g, int64_t in_k, double2* out, int64_t out_b, int64_t out_g, int64_t out_k,
+              hipStream_t st) {
+  CapArgs ca;
+  ca.nb = nb;
+  ca.G = G;
+  ca.nL = p->nL;
+  ca.T0 = T0;
+  ca.T1 = T1;
+  ca.in = in;
+  ca.in_b = in_b;
+  ca.in_g = in_g;
+  ca.in_k = in_k;
+  ca.out = out;
+  ca.out_b = out_b;
+  ca.out_g = out_g;
+  ca.out_k = out_k;
+  ca.skip = p->skip_cur;
+  const double by = 2.0 * G * (2.0 * p->nL) * p->nL * sizeof(double2) * ((nb + 15) / 16);
+  HCHK(timed(p, K_CAP, by, st, [&] { return launch_cap_apply(ca, st); }));
+  return HELM_OK;
+}
 
 int inner_solve(helm_plan* p, const Level& lv, const InnerIO& io, hipStream_t st) {
   const PAxis& I = *lv.inner;
@@ -829,25 +865,34 @@ int inner_solve(helm_plan* p, const Level& lv, const InnerIO& io, hipStream_t st
   HCHK(timed(p, K_INNER_MID, (double)lv.nb * lv.nO * 2 * lv.nL * sizeof(double2) * (nt + 2), st,
              [&] { return launch_inner_mid(m, st); }));
 
-  // S2: partial solution with the absorbing-boundary eigenvectors.
-  LineArgs s2 = base;
-  s2.sI = I.sigA;
-  s2.piv = io.seedA;
-  s2.sTab = io.sigTA;
-  s2.PI = p->PIb.as<double2>();
-  s2.beta0 = I.va0d;
-  s2.beta1 = I.va1d;
-  s2.red = 1;
-  s2.rho0 = I.va0d;
-  s2.rho1 = I.va1d;
-  s2.part = part;
-  s2.tile = tile;
-  s2.ntiles = nt;
-  HCHK(timed(p, K_LINES, 0.0, st, [&] { return launch_lines(s2, st); }));
+  // S2: partial solution with the absorbing-boundary eigenvectors, as a
+  // line sweep or from the table of its map (one partial per (b, l))
+  if (io.capS2) {
+    const int64_t per = 2 * (int64_t)lv.nL, gs = (int64_t)lv.nO * per;
+    const int rc2 = cap_apply(p, p->capW0, p->capW1, lv.nb, lv.nO, p->PIb.as<double2>(), gs, per, lv.nL, part, gs,
+                              per, lv.nL, st);
+    if (rc2) return rc2;
+    m.ntiles = 1;
+  } else {
+    LineArgs s2 = base;
+    s2.sI = I.sigA;
+    s2.piv = io.seedA;
+    s2.sTab = io.sigTA;
+    s2.PI = p->PIb.as<double2>();
+    s2.beta0 = I.va0d;
+    s2.beta1 = I.va1d;
+    s2.red = 1;
+    s2.rho0 = I.va0d;
+    s2.rho1 = I.va1d;
+    s2.part = part;
+    s2.tile = tile;
+    s2.ntiles = nt;
+    HCHK(timed(p, K_LINES, 0.0, st, [&] { return launch_lines(s2, st); }));
+  }
 
   m.vb_in = p->VB.as<double2>();
   m.vb_out = nullptr;
-  HCHK(timed(p, K_INNER_MID, (double)lv.nb * lv.nO * 2 * lv.nL * sizeof(double2) * (nt + 2), st,
+  HCHK(timed(p, K_INNER_MID, (double)lv.nb * lv.nO * 2 * lv.nL * sizeof(double2) * (m.ntiles + 2), st,
              [&] { return launch_inner_mid(m, st); }));
 
   // S3: corrected periodic solve.
@@ -1029,9 +1074,12 @@ int solve_once(helm_plan* p, const void* x, int x_kind, double2* u, int accumula
   double2* Rh = p->P3.as<double2>();
   const double2* d_null = nullptr;
   (void)d_null;
+  // Boundary steps from the plan's tables for this many right-hand sides?
+  const bool cap = p->cap_min_nb > 0 && nb >= p->cap_min_nb;
   // Outer step 1: v_b.
   {
     InnerIO io;
+    io.capS2 = cap;
     io.sO = A1.sigB;
     io.seedB = p->seed[0];
     io.seedA = p->seed[1];
@@ -1068,27 +1116,40 @@ int solve_once(helm_plan* p, const void* x, int x_kind, double2* u, int accumula
     om.k3Lo = p->kLo;
     om.k3Hi = p->kHi;
     HCHK(timed(p, K_OUTER_MID, (double)nb * 2 * plane * sizeof(double2) * 3, st, [&] { return launch_outer_mid(om, st); }));
-    rc = run_fft(p, A2, -1, false, Wp, ST_C128, Rh, ST_C128, (int64_t)nb * 2, n3, A2.invmu, 1.0, 0, Vh,
-                 ST_C128, st);
-    if (rc) return rc;
-    InnerIO io;
-    io.sO = A1.sigA;
-    io.seedB = p->seed[2];
-    io.seedA = p->seed[3];
-    io.sigTB = p->sig[2];
-    io.sigTA = p->sig[3];
-    io.PO = Rh;
-    io.alpha0 = A1.va0d;
-    io.alpha1 = A1.va1d;
-    io.rhoL0 = A1.va0d;
-    io.rhoL1 = A1.va1d;
-    rc = inner_solve(p, lv, io, st);
-    if (rc) return rc;
-    rc = sum_to_planes(p, lv, Vh, st);
-    if (rc) return rc;
-    rc = run_fft(p, A2, +1, false, Vh, ST_C128, Wp, ST_C128, (int64_t)nb * 2, n3, nullptr, 1.0 / n2, 0,
-                 Rh, ST_C128, st);
-    if (rc) return rc;
+    if (cap) {
+      // w_b = sum_l V1b[:, l] A_l^{-1} g_l with the inner absorbing
+      // eigenvectors: A_l^{-1} = (V2 (x) I) blockdiag_m T_lm^{-1} (V2^T (x) I),
+      // so w_b = (V2 (x) I) H_m (V2^T (x) I) r with the table H of
+      // sum_l V1b[k, l] V1b[k', l] T_lm^{-1} per inner mode m
+      rc = dense_pass(p, n2, n3, (int64_t)nb * 2, A2.Vd, Wp, ST_C128, Rh, ST_C128, 0, false, st);
+      if (rc) return rc;
+      rc = cap_apply(p, p->capH0, p->capH1, nb, n2, Rh, 2 * plane, n3, plane, Vh, 2 * plane, n3, plane, st);
+      if (rc) return rc;
+      rc = dense_pass(p, n2, n3, (int64_t)nb * 2, A2.VTd, Vh, ST_C128, Wp, ST_C128, 0, false, st);
+      if (rc) return rc;
+    } else {
+      rc = run_fft(p, A2, -1, false, Wp, ST_C128, Rh, ST_C128, (int64_t)nb * 2, n3, A2.invmu, 1.0, 0, Vh,
+                   ST_C128, st);
+      if (rc) return rc;
+      InnerIO io;
+      io.sO = A1.sigA;
+      io.seedB = p->seed[2];
+      io.seedA = p->seed[3];
+      io.sigTB = p->sig[2];
+      io.sigTA = p->sig[3];
+      io.PO = Rh;
+      io.alpha0 = A1.va0d;
+      io.alpha1 = A1.va1d;
+      io.rhoL0 = A1.va0d;
+      io.rhoL1 = A1.va1d;
+      rc = inner_solve(p, lv, io, st);
+      if (rc) return rc;
+      rc = sum_to_planes(p, lv, Vh, st);
+      if (rc) return rc;
+      rc = run_fft(p, A2, +1, false, Vh, ST_C128, Wp, ST_C128, (int64_t)nb * 2, n3, nullptr, 1.0 / n2, 0,
+                   Rh, ST_C128, st);
+      if (rc) return rc;
+    }
     // q = C_1 (v_b + w_b), transformed along x_2 and scaled by 1/mu_2
     om.a = Vp;
     om.c = Wp;
@@ -1101,6 +1162,7 @@ int solve_once(helm_plan* p, const void* x, int x_kind, double2* u, int accumula
   // Outer step 3: corrected periodic solve, stored, then inverse transforms.
   {
     InnerIO io;
+    io.capS2 = cap;
     io.sO = A1.sigB;
     io.seedB = p->seed[0];
     io.seedA = p->seed[1];
@@ -1466,6 +1528,12 @@ int capture_solve(helm_plan* p, const double2* F, double2* U, int nb, hipStream_
   return HELM_OK;
 }
 
+// How the boundary steps of a solve of nrhs right-hand sides run.
+int boundary_used(const helm_plan* p, int nrhs) {
+  return (p->dim == 3 && !p->dense && p->cap_min_nb > 0 && nrhs >= p->cap_min_nb) ? HELM_BOUNDARY_TABLES
+                                                                                   : HELM_BOUNDARY_LINES;
+}
+
 // Refinement on the host: while the residual exceeds tol, solve for the
 // residual (stored in R by the last residual_norms) and add the correction
 // to u; stop at tol, at max_iter steps, or when a step fails to halve the
@@ -1511,6 +1579,7 @@ int solve_entry(helm_plan* p, const void* f, void* u, int nrhs, hipStream_t st, 
   rep = helm_report{};
   rep.precision = p->opt.precision;
   rep.transform = p->dense ? HELM_TRANSFORM_DENSE : HELM_TRANSFORM_FFT;
+  rep.boundary = boundary_used(p, nrhs);
   rep.nrhs = nrhs;
   rep.rel_residual_max = -1;
   rep.rel_residual_first = -1;
@@ -1662,6 +1731,7 @@ int solve_static(helm_plan* p, const void* f, void* u, int nrhs, hipStream_t st)
   rep = helm_report{};
   rep.precision = p->opt.precision;
   rep.transform = p->dense ? HELM_TRANSFORM_DENSE : HELM_TRANSFORM_FFT;
+  rep.boundary = boundary_used(p, nrhs);
   rep.nrhs = nrhs;
   rep.rel_residual_max = -1;
   rep.rel_residual_first = -1;
@@ -1704,22 +1774,241 @@ std::string tune_key(const helm_plan* p) {
   return buf;
 }
 
-bool tune_lookup(const std::string& path, const std::string& key, int* choice) {
+// Value of `field` (e.g. "transform=") on the last cache line for this key.
+bool tune_lookup(const std::string& path, const std::string& key, const char* field, int* value) {
   FILE* f = std::fopen(path.c_str(), "r");
   if (!f) return false;
-  const std::string pre = "helm-tune " + key + " transform=";
+  const std::string pre = "helm-tune " + key + " " + field;
   char line[512];
   bool found = false;
   while (std::fgets(line, sizeof line, f)) {
     if (std::strncmp(line, pre.c_str(), pre.size()) != 0) continue;
-    const int t = std::atoi(line + pre.size());
-    if (t == HELM_TRANSFORM_FFT || t == HELM_TRANSFORM_DENSE) {
-      *choice = t;
-      found = true;  // the last matching line wins
-    }
+    *value = std::atoi(line + pre.size());
+    found = true;  // the last matching line wins
   }
   std::fclose(f);
   return found;
+}
+
+bool tune_lookup(const std::string& path, const std::string& key, int* choice) {
+  int t = 0;
+  if (!tune_lookup(path, key, "transform=", &t)) return false;
+  if (t != HELM_TRANSFORM_FFT && t != HELM_TRANSFORM_DENSE) return false;
+  *choice = t;
+  return true;
+}
+
+// ---------------------------------------------------------------------------
+// Boundary operator tables (3D).  W_l^{kk'} = sum_m V2b[k,m] V2b[k',m]
+// (T^{BA}_lm)^{-1} maps the inner boundary vectors to the inner Step-2
+// result of outer mode l; H_m^{kk'} = sum_l V1b[k,l] V1b[k',l] (T^{AA}_lm)^{-1}
+// maps the inner absorbing mode m of the outer boundary planes to that of the
+// outer Step-2 result.  Column x' of each is the reduction of the line
+// solutions with the unit right-hand side e_{x'}: one line launch per k'
+// with nL "right-hand sides".
+// ---------------------------------------------------------------------------
+int build_boundary_tables(helm_plan* p) {
+  const PAxis& A1 = p->ax[0];
+  const PAxis& A2 = p->ax[1];
+  const int n1 = A1.n, n2 = A2.n, nL = p->nL;
+  std::vector<double2> w((size_t)3 * (n1 + n2));
+  for (int m = 0; m < n2; ++m) {
+    w[m] = hd2(A2.va0[m] * A2.va0[m]);
+    w[n2 + m] = hd2(A2.va0[m] * A2.va1[m]);
+    w[2 * n2 + m] = hd2(A2.va1[m] * A2.va1[m]);
+  }
+  double2* d1 = w.data() + 3 * n2;
+  for (int l = 0; l < n1; ++l) {
+    d1[l] = hd2(A1.va0[l] * A1.va0[l]);
+    d1[n1 + l] = hd2(A1.va0[l] * A1.va1[l]);
+    d1[2 * n1 + l] = hd2(A1.va1[l] * A1.va1[l]);
+  }
+  DevMem wt;
+  HCHK(wt.ensure(w.size() * sizeof(double2)));
+  HCHK(upload(wt.p, w.data(), w.size() * sizeof(double2)));
+  const double2* c = wt.as<double2>();        // c00, c01, c11 over m
+  const double2* dd = c + 3 * (size_t)n2;     // d00, d01, d11 over l
+  const size_t blkW = (size_t)nL * n1 * 2 * nL, blkH = (size_t)nL * n2 * 2 * nL;
+  HCHK(p->capW.ensure(2 * blkW * sizeof(double2)));
+  HCHK(p->capH.ensure(2 * blkH * sizeof(double2)));
+  p->capW0 = p->capW.as<double2>();
+  p->capW1 = p->capW0 + blkW;
+  p->capH0 = p->capH.as<double2>();
+  p->capH1 = p->capH0 + blkH;
+  DevMem part;
+  HCHK(part.ensure(std::max(part_elems(1, nL, n1, n2, nL), part_elems(2, nL, n1, n2, nL)) * sizeof(double2)));
+  LineArgs base;
+  base.nb = nL;
+  base.nO = n1;
+  base.nI = n2;
+  base.nL = nL;
+  base.hL = p->hL;
+  base.kLo = p->kLo;
+  base.kHi = p->kHi;
+  base.unit_rhs = 1;
+  base.part = part.as<double2>();
+  for (int kp = 0; kp < 2; ++kp) {
+    LineArgs la = base;  // W: lines of the (B, A) family, reduced over m
+    la.sTab = p->sig[1];
+    la.piv = p->seed[1];
+    la.red = 1;
+    la.rho0 = kp ? c + n2 : c;
+    la.rho1 = kp ? c + 2 * n2 : c + n2;
+    tiles_for(1, nL, n1, n2, nL, &la.tile, &la.ntiles);
+    HCHK(launch_lines(la, nullptr));
+    HCHK(launch_sum_partials(base.part, nL * n1, la.ntiles, nL, const_cast<double2*>(kp ? p->capW1 : p->capW0),
+                             nullptr, nullptr));
+  }
+  for (int kp = 0; kp < 2; ++kp) {
+    LineArgs la = base;  // H: lines of the (A, A) family, reduced over l
+    la.sTab = p->sig[3];
+    la.piv = p->seed[3];
+    la.red = red_l_mode(nL, n2, nL);
+    la.rho0 = kp ? dd + n1 : dd;
+    la.rho1 = kp ? dd + 2 * n1 : dd + n1;
+    tiles_for(2, nL, n1, n2, nL, &la.tile, &la.ntiles);
+    HCHK(launch_lines(la, nullptr));
+    HCHK(launch_sum_partials(base.part, nL * n2, la.ntiles, nL, const_cast<double2*>(kp ? p->capH1 : p->capH0),
+                             nullptr, nullptr));
+  }
+  HCHK(hipDeviceSynchronize());
+  return HELM_OK;
+}
+
+// Times (ms, best of 3 after a warm-up) of the boundary work of one 3D solve
+// of nb right-hand sides that the tables replace: 5 Step-2-like line sweeps
+// (measured as one sweep times 5) against two capW products, one capH
+// product and the two inner eigenvector transforms of the boundary planes.
+int measure_boundary(helm_plan* p, int nb, double* t_lines, double* t_tab) {
+  const PAxis& A2 = p->ax[1];
+  const int n1 = p->ax[0].n, n2 = A2.n, nL = p->nL;
+  const int64_t per = 2 * (int64_t)nL, plane = (int64_t)n2 * nL;
+  DevMem pi, part, pa, pb;
+  HCHK(pi.ensure((size_t)nb * n1 * per * sizeof(double2)));
+  HCHK(part.ensure(part_elems(1, nb, n1, n2, nL) * sizeof(double2)));
+  HCHK(pa.ensure((size_t)nb * 2 * plane * sizeof(double2)));
+  HCHK(pb.ensure((size_t)nb * 2 * plane * sizeof(double2)));
+  HCHK(hipMemset(pi.p, 0x3f, pi.bytes));  // finite values of order 1e-3
+  HCHK(hipMemset(pa.p, 0x3f, pa.bytes));
+  LineArgs s2;
+  s2.nb = nb;
+  s2.nO = n1;
+  s2.nI = n2;
+  s2.nL = nL;
+  s2.hL = p->hL;
+  s2.kLo = p->kLo;
+  s2.kHi = p->kHi;
+  s2.sTab = p->sig[1];
+  s2.piv = p->seed[1];
+  s2.PI = pi.as<double2>();
+  s2.beta0 = A2.va0d;
+  s2.beta1 = A2.va1d;
+  s2.red = 1;
+  s2.rho0 = A2.va0d;
+  s2.rho1 = A2.va1d;
+  s2.part = part.as<double2>();
+  tiles_for(1, nb, n1, n2, nL, &s2.tile, &s2.ntiles);
+  auto lines = [&]() -> int {
+    HCHK(launch_lines(s2, nullptr));
+    return HELM_OK;
+  };
+  auto tab = [&]() -> int {
+    const int64_t gs = (int64_t)n1 * per;
+    for (int k = 0; k < 2; ++k) {
+      const int rc = cap_apply(p, p->capW0, p->capW1, nb, n1, pi.as<double2>(), gs, per, nL, part.as<double2>(),
+                               gs, per, nL, nullptr);
+      if (rc) return rc;
+    }
+    int rc = dense_pass(p, n2, nL, (int64_t)nb * 2, A2.Vd, pa.p, ST_C128, pb.p, ST_C128, 0, false, nullptr);
+    if (rc) return rc;
+    rc = cap_apply(p, p->capH0, p->capH1, nb, n2, pb.as<double2>(), 2 * plane, nL, plane, pa.as<double2>(),
+                   2 * plane, nL, plane, nullptr);
+    if (rc) return rc;
+    return dense_pass(p, n2, nL, (int64_t)nb * 2, A2.VTd, pa.p, ST_C128, pb.p, ST_C128, 0, false, nullptr);
+  };
+  hipEvent_t e0, e1;
+  HCHK(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return HELM_EDEVICE;
+  }
+  int rc = HELM_OK;
+  double best[2] = {1e30, 1e30};
+  for (int which = 0; which < 2 && !rc; ++which) {
+    for (int rep = 0; rep < 4 && !rc; ++rep) {
+      if (hipEventRecord(e0, nullptr) != hipSuccess) { rc = HELM_EDEVICE; break; }
+      rc = which == 0 ? lines() : tab();
+      if (rc) break;
+      float ms = 0;
+      if (hipEventRecord(e1, nullptr) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+          hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+        rc = HELM_EDEVICE;
+        break;
+      }
+      if (rep > 0) best[which] = std::min(best[which], (double)ms);
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  *t_lines = 5.0 * best[0];
+  *t_tab = best[1];
+  return rc;
+}
+
+// Builds the tables when they fit the budget and decides from which number
+// of right-hand sides solves use them (helm_options.boundary).
+int setup_boundary_tables(helm_plan* p) {
+  const bool forced = p->opt.boundary == HELM_BOUNDARY_TABLES;
+  const int n1 = p->ax[0].n, n2 = p->ax[1].n, nL = p->nL;
+  if ((int64_t)nL * n1 * n2 >= 0x7fffffffLL) return forced ? HELM_EUNSUPPORTED : HELM_OK;
+  const double bytes = 64.0 * nL * nL * (double)(n1 + n2);
+  size_t fr = 0, tot = 0;
+  if (hipMemGetInfo(&fr, &tot) != hipSuccess) return HELM_EDEVICE;
+  const double budget = std::min(32.0 * (double)(1ull << 30), 0.25 * (double)fr);
+  if (!forced && bytes > budget) return HELM_OK;
+  const std::string key = tune_key(p);
+  int cached = -1;
+  if (!forced && !p->tune_path.empty() && tune_lookup(p->tune_path, key, "boundary cap_min_nb=", &cached) &&
+      cached == 0)
+    return HELM_OK;  // measured before: the tables never pay for this shape
+  int rc = build_boundary_tables(p);
+  if (rc) return rc;
+  if (forced) {
+    p->cap_min_nb = 1;
+    return HELM_OK;
+  }
+  if (cached > 0) {
+    p->cap_min_nb = cached;
+    return HELM_OK;
+  }
+  // time both forms at 1 and 16 right-hand sides; both grow linearly with nb
+  rc = measure_boundary(p, 1, &p->cap_ms[0], &p->cap_ms[2]);
+  if (!rc) rc = measure_boundary(p, 16, &p->cap_ms[1], &p->cap_ms[3]);
+  if (rc) return rc;
+  const double bl = (p->cap_ms[1] - p->cap_ms[0]) / 15.0, al = p->cap_ms[0] - bl;
+  const double bt = (p->cap_ms[3] - p->cap_ms[2]) / 15.0, at = p->cap_ms[2] - bt;
+  int nmin = 0;
+  if (p->cap_ms[2] < p->cap_ms[0]) {
+    nmin = 1;
+  } else if (bl > bt) {
+    const double x = (at - al) / (bl - bt);  // tables win above x right-hand sides
+    nmin = x < 1e6 ? (int)std::floor(x) + 1 : 0;
+  }
+  p->cap_min_nb = nmin;
+  if (nmin == 0) {  // never pays: give the memory back
+    p->capW.release();
+    p->capH.release();
+    p->capW0 = p->capW1 = p->capH0 = p->capH1 = nullptr;
+  }
+  if (!p->tune_path.empty()) {
+    FILE* f = std::fopen(p->tune_path.c_str(), "a");
+    if (f) {
+      std::fprintf(f, "helm-tune %s boundary cap_min_nb=%d lines_ms_1=%.6g lines_ms_16=%.6g tables_ms_1=%.6g "
+                   "tables_ms_16=%.6g\n", key.c_str(), nmin, p->cap_ms[0], p->cap_ms[1], p->cap_ms[2], p->cap_ms[3]);
+      std::fclose(f);
+    }
+  }
+  return HELM_OK;
 }
 
 int autotune_transform(helm_plan* p) {
@@ -1827,6 +2116,7 @@ void helm_default_options(helm_options* opt) {
   opt->check = 1;
   opt->transform = HELM_TRANSFORM_FFT;
   opt->tune_cache = nullptr;
+  opt->boundary = HELM_BOUNDARY_AUTO;
 }
 
 const char* helm_strerror(int code) {
@@ -1865,6 +2155,10 @@ int helm_setup(int dim, const int64_t* grid, const double* h, double omega, uint
   if (p->opt.max_iter < 0 || !(p->opt.tol >= 0.0)) return HELM_EINVAL;
   const int tf = p->opt.transform;
   if (tf != HELM_TRANSFORM_AUTO && tf != HELM_TRANSFORM_FFT && tf != HELM_TRANSFORM_DENSE) return HELM_EINVAL;
+  const int bmode = p->opt.boundary;
+  if (bmode != HELM_BOUNDARY_AUTO && bmode != HELM_BOUNDARY_LINES && bmode != HELM_BOUNDARY_TABLES)
+    return HELM_EINVAL;
+  const bool want_tab = dim == 3 && bmode != HELM_BOUNDARY_LINES && tf != HELM_TRANSFORM_DENSE;
   if (p->opt.tune_cache) p->tune_path = p->opt.tune_cache;
   p->opt.tune_cache = nullptr;
   bool dense_ok = tf != HELM_TRANSFORM_FFT;
@@ -1905,13 +2199,16 @@ int helm_setup(int dim, const int64_t* grid, const double* h, double omega, uint
       if (bst != HELM_OK) return bst;
     }
     std::vector<cd> vfull, lamlo;
-    const int st = eig1d(a.n, a.h, omega, a.lo, a.hi, a.lamA, a.va0, a.va1, dense_ok ? &vfull : nullptr, &lamlo);
+    // whole eigenvectors: both axes for the dense transform, the inner one
+    // for the boundary tables
+    const bool vecs = dense_ok || (want_tab && j == 1);
+    const int st = eig1d(a.n, a.h, omega, a.lo, a.hi, a.lamA, a.va0, a.va1, vecs ? &vfull : nullptr, &lamlo);
     if (st != HELM_OK) return st;
     a.lamAx.resize(a.n);
     for (int l = 0; l < a.n; ++l)
       a.lamAx[l] = std::complex<long double>((long double)a.lamA[l].real() + lamlo[l].real(),
                                              (long double)a.lamA[l].imag() + lamlo[l].imag());
-    if (dense_ok) {
+    if (vecs) {
       const int ast = upload_eigvecs(a, vfull);
       if (ast != HELM_OK) return ast;
     }
@@ -1982,6 +2279,10 @@ int helm_setup(int dim, const int64_t* grid, const double* h, double omega, uint
       p->seed[k] = dst;
     }
     if (hipDeviceSynchronize() != hipSuccess) return HELM_EDEVICE;
+  }
+  if (want_tab) {
+    const int brc = setup_boundary_tables(p.get());
+    if (brc != HELM_OK) return brc;
   }
   if (prepare_roots(p.get()) != HELM_OK) return HELM_ENOMEM;
   if (hipHostMalloc(reinterpret_cast<void**>(&p->h_norms_pin), 2 * HELM_STATIC_MAX_RHS * sizeof(double),
@@ -2058,8 +2359,9 @@ int helm_kernel_stats_get(helm_plan* p, helm_kernel_stats* out, int reset) {
 
 const char* helm_kernel_name(int k) {
   static const char* names[HELM_NKERNELS] = {
-      "fft_pass_kernel<double2>", "fft_pass_kernel<float2>", "lines_kernel", "inner_mid_kernel",
-      "sum_to_planes_kernel",     "outer_mid_kernel",        "residual_kernel", "dense_kernel"};
+      "fft_pass_kernel<double2>", "fft_pass_kernel<float2>", "lines_kernel",    "inner_mid_kernel",
+      "sum_to_planes_kernel",     "outer_mid_kernel",        "residual_kernel", "dense_kernel",
+      "cap_apply_kernel"};
   return (k >= 0 && k < HELM_NKERNELS) ? names[k] : nullptr;
 }
 
@@ -2195,6 +2497,7 @@ int helm_batch_report_get(helm_batch* b, int i, helm_report* out) {
   r.iterations = c.iters;
   r.precision = p->opt.precision;
   r.transform = p->dense ? HELM_TRANSFORM_DENSE : HELM_TRANSFORM_FFT;
+  r.boundary = boundary_used(p, b->kn[i]);
   r.nrhs = b->kn[i];
   r.rel_residual_max = c.rel_last;
   r.rel_residual_first = c.rel_first;

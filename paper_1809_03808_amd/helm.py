@@ -29,6 +29,9 @@ TRANSFORM_AUTO = 0
 TRANSFORM_FFT = 1
 TRANSFORM_DENSE = 2
 DENSE_MAX = 1024
+BOUNDARY_AUTO = 0
+BOUNDARY_LINES = 1
+BOUNDARY_TABLES = 2
 
 # Every symbol declared in include/helm.h.
 EXPORTS = (
@@ -42,13 +45,14 @@ EXPORTS = (
 STATIC_SCRATCH_BYTES = 128 << 20
 STATIC_MAX_RHS = 1024
 
-NKERNELS = 8
+NKERNELS = 9
 
 
 class Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("tol", ctypes.c_double),
                 ("max_iter", ctypes.c_int), ("check", ctypes.c_int),
-                ("transform", ctypes.c_int), ("tune_cache", ctypes.c_char_p)]
+                ("transform", ctypes.c_int), ("tune_cache", ctypes.c_char_p),
+                ("boundary", ctypes.c_int)]
 
 
 class Report(ctypes.Structure):
@@ -56,12 +60,12 @@ class Report(ctypes.Structure):
                 ("precision", ctypes.c_int), ("nrhs", ctypes.c_int),
                 ("rel_residual_max", ctypes.c_double),
                 ("rel_residual_first", ctypes.c_double),
-                ("transform", ctypes.c_int)]
+                ("transform", ctypes.c_int), ("boundary", ctypes.c_int)]
 
 
 class KernelStats(ctypes.Structure):
-    _fields_ = [("ms", ctypes.c_double * 8), ("bytes", ctypes.c_double * 8),
-                ("calls", ctypes.c_int * 8)]
+    _fields_ = [("ms", ctypes.c_double * 9), ("bytes", ctypes.c_double * 9),
+                ("calls", ctypes.c_int * 9)]
 
 
 class HelmError(RuntimeError):
@@ -169,7 +173,7 @@ class Plan:
     """A solver plan: ``Plan(grid, h, omega, abc)`` then ``plan.solve(f, u)``."""
 
     def __init__(self, grid, h, omega, abc=None, precision=PREC_FP64, tol=1e-10, max_iter=8,
-                 check=True, transform=None, tune_cache=None):
+                 check=True, transform=None, tune_cache=None, boundary=None):
         L = lib()
         self.grid = tuple(int(n) for n in grid)
         self.dim = len(self.grid)
@@ -186,6 +190,8 @@ class Plan:
         opt.check = int(bool(check))
         if transform is not None:
             opt.transform = int(transform)
+        if boundary is not None:
+            opt.boundary = int(boundary)
         self._tune = tune_cache.encode() if tune_cache else None
         opt.tune_cache = self._tune
         g = (ctypes.c_int64 * self.dim)(*self.grid)

@@ -38,6 +38,13 @@ def test_strerror_and_defaults():
     opt = helm.Options()
     helm.lib().helm_default_options(ctypes.byref(opt))
     assert opt.precision == helm.PREC_FP64 and opt.tol == 1e-10 and opt.max_iter == 8 and opt.check == 1
+    assert opt.transform == helm.TRANSFORM_FFT and opt.boundary == helm.BOUNDARY_AUTO
+
+
+def test_setup_rejects_unknown_boundary_mode():
+    with pytest.raises(helm.HelmError) as e:
+        helm.Plan((8, 8, 8), (0.1,) * 3, 3.0, boundary=7)
+    assert e.value.code == helm.HELM_EINVAL
 
 
 def test_eig1d_rejects_bad_arguments():

@@ -294,3 +294,59 @@ def test_nonfinite_rhs_reported():
     f[0, 3, 4] = np.nan
     rc, rep, u, h = _run(grid, 8.0, 0b1111, f)
     assert rc == helm.HELM_ENONFINITE
+
+
+TABLE_CASES = [
+    ((8, 8, 9), 6.0, 0b111111, 1),
+    ((12, 10, 9), 8.0, 0b111111, 3),
+    ((8, 16, 7), 10.0, 0b110111, 2),   # x2 low face Neumann
+    ((20, 16, 11), 12.0, 0b011111, 5),  # x3 high face Neumann
+    ((3, 257, 5), 40.0, 0b111111, 1),   # chirp-z along x2
+    ((3, 4, 512), 150.0, 0b111111, 4),  # exact 64-lane lines
+    ((3, 3, 513), 150.0, 0b111111, 2),  # 8 P + 1 rows
+    ((6, 5, 300), 30.0, 0b111111, 17),  # padded lines; more than 16 right-hand sides
+]
+
+
+@pytest.mark.parametrize("prec", [helm.PREC_FP64, helm.PREC_MIXED])
+@pytest.mark.parametrize("grid,omega,mask,nrhs", TABLE_CASES)
+def test_3d_boundary_tables_match_banded_lu(grid, omega, mask, nrhs, prec):
+    """The boundary steps from the precomputed tables (inner Step 2 per outer
+    mode, outer Step 2 per inner absorbing mode) against the oracle."""
+    grid = tuple(grid)
+    h = inputs.spacing(grid)
+    f = inputs.gaussian_batch(grid, [70 + r for r in range(nrhs)]).astype(np.complex128)
+    _say("tables case", grid, omega, bin(mask), "prec", prec, "nrhs", nrhs)
+    with helm.Plan(grid, h, omega, mask, precision=prec, check=False, boundary=helm.BOUNDARY_TABLES) as plan:
+        fd = torch.from_numpy(f).to("cuda")
+        ud = torch.empty_like(fd)
+        rc = plan.solve(fd, ud, raise_on_error=False)
+        rep = plan.report()
+        u = ud.cpu().numpy()
+    ref = _oracle(grid, h, omega, mask, f)
+    err = fem.rel_error(u.reshape(nrhs, -1), ref.reshape(nrhs, -1))
+    _say("  tables rel err", np.max(err), "report", rep)
+    assert rc == helm.HELM_OK and rep["boundary"] == helm.BOUNDARY_TABLES
+    if prec == helm.PREC_FP64:
+        assert np.max(err) <= 1e-9
+    else:
+        res = fem.rel_residual(grid, h, omega, _abc_tuple(3, mask), u.reshape(nrhs, -1), f.reshape(nrhs, -1))
+        assert np.max(res) <= 1e-10 and np.max(err) <= 1e-8
+
+
+def test_3d_boundary_tables_equal_line_sweeps_closely():
+    """Same problem, tables against line sweeps: the two evaluations of the
+    boundary maps agree to rounding."""
+    grid, omega, mask = (16, 16, 64), 20.0, 0b111111
+    h = inputs.spacing(grid)
+    f = torch.from_numpy(inputs.gaussian_batch(grid, [90, 91, 92, 93])).cuda()
+    out = {}
+    for b in (helm.BOUNDARY_LINES, helm.BOUNDARY_TABLES):
+        with helm.Plan(grid, h, omega, mask, check=False, boundary=b) as plan:
+            u = torch.empty_like(f)
+            plan.solve(f, u)
+            out[b] = u
+            assert plan.report()["boundary"] == b
+    d = (torch.linalg.vector_norm(out[1] - out[2]) / torch.linalg.vector_norm(out[1])).item()
+    _say("  ||u_tables - u_lines|| / ||u_lines|| =", d)
+    assert d <= 1e-12

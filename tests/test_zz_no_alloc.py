@@ -20,7 +20,8 @@ def _say(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-KEYS = ("status", "iterations", "precision", "nrhs", "rel_residual_max", "rel_residual_first", "transform")
+KEYS = ("status", "iterations", "precision", "nrhs", "rel_residual_max", "rel_residual_first", "transform",
+        "boundary")
 
 
 def _compare(plan, fd, tag):
