@@ -84,7 +84,8 @@ extern "C" {
  *           Step 2, the latter after the dense inner eigenvector transform of
  *           the two boundary planes) and apply it as a batched matrix product:
  *           5 of the 9 line sweeps of a 3D solve become products with
- *           64 n_3^2 (n_1 + n_2) bytes of tables;
+ *           64 n_3^2 (n_1 + n_2) bytes of tables
+ *           (complex128; half that, complex64, for HELM_PREC_MIXED plans);
  *   AUTO    build the tables when they fit the memory budget (at most 32 GiB
  *           and a quarter of the free device memory) and use them for solves
  *           of at least as many right-hand sides as the plan measured them to

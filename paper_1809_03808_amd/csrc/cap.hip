@@ -32,10 +32,12 @@ constexpr int kCapThreads = 256;
 // Register tile: each lane computes 4 rows (r0 + lane + 64 i) times TN
 // right-hand sides; RG waves of a block share its rows and take consecutive
 // groups of TN right-hand sides, so a block covers 256 * 4 / RG rows and
-// RG * TN right-hand sides per pass over the table.
-template <int TN, int RG>
-__global__ __launch_bounds__(kCapThreads) void cap_apply_kernel(const double2* __restrict__ T0,
-                                                                const double2* __restrict__ T1,
+// RG * TN right-hand sides per pass over the table.  Table entries of type
+// TT (complex128, or complex64 for the mixed-precision path) are widened to
+// FP64 and accumulated in FP64.
+template <typename TT, int TN, int RG>
+__global__ __launch_bounds__(kCapThreads) void cap_apply_kernel(const TT* __restrict__ T0,
+                                                                const TT* __restrict__ T1,
                                                                 const double2* __restrict__ in,
                                                                 double2* __restrict__ out, CapArgs a) {
   constexpr int TM = 4;
@@ -47,7 +49,6 @@ __global__ __launch_bounds__(kCapThreads) void cap_apply_kernel(const double2* _
   const int wv = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
   const int rg = wv % RG;
   const int rbase = (int)(blockIdx.x % rt) * RPB + (wv / RG) * 64 * TM + ((int)threadIdx.x & 63);
-  const int64_t ts = (int64_t)a.G * rows;  // stride between x' rows of a table
   for (int b0 = rg * TN; b0 < a.nb; b0 += RG * TN) {
     double2 acc[TM][TN];
 #pragma unroll
@@ -55,7 +56,7 @@ __global__ __launch_bounds__(kCapThreads) void cap_apply_kernel(const double2* _
 #pragma unroll
       for (int j = 0; j < TN; ++j) acc[i][j] = make_double2(0, 0);
     for (int kp = 0; kp < 2; ++kp) {
-      const double2* T = (kp ? T1 : T0) + (int64_t)g * rows;
+      const TT* T = (kp ? T1 : T0) + (int64_t)g * nL * rows;  // this group's [x'][rows] block
       // uniform (scalar) pointers to this wave's right-hand sides; those past
       // nb repeat the last one and their products are dropped
       const double2* X[TN];
@@ -69,7 +70,7 @@ __global__ __launch_bounds__(kCapThreads) void cap_apply_kernel(const double2* _
       for (int xp = 0; xp < nL; ++xp) {
         double2 t[TM];
 #pragma unroll
-        for (int i = 0; i < TM; ++i) t[i] = T[(int64_t)xp * ts + ro[i]];
+        for (int i = 0; i < TM; ++i) t[i] = to_d2(T[(int64_t)xp * rows + ro[i]]);
 #pragma unroll
         for (int j = 0; j < TN; ++j) {
           const double2 v = X[j][xp];
@@ -92,28 +93,58 @@ __global__ __launch_bounds__(kCapThreads) void cap_apply_kernel(const double2* _
   }
 }
 
-template <int TN, int RG>
+template <typename TT, int TN, int RG>
 hipError_t launch_nbc(const CapArgs& a, hipStream_t s) {
   constexpr int RPB = 64 * 4 * (4 / RG);
   const int64_t blocks = (int64_t)a.G * ((2 * a.nL + RPB - 1) / RPB);
   if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((cap_apply_kernel<TN, RG>), dim3((unsigned)blocks), dim3(kCapThreads), 0, s, a.T0, a.T1,
-                     a.in, a.out, a);
+  hipLaunchKernelGGL((cap_apply_kernel<TT, TN, RG>), dim3((unsigned)blocks), dim3(kCapThreads), 0, s,
+                     reinterpret_cast<const TT*>(a.T0), reinterpret_cast<const TT*>(a.T1), a.in, a.out, a);
   return hipGetLastError();
+}
+
+template <typename TT>
+hipError_t launch_typed(const CapArgs& a, hipStream_t s) {
+  // TN right-hand sides per wave (the smallest power of two covering nb, at
+  // most 4) and RG waves sharing rows: up to 16 right-hand sides per pass
+  // over the table, more in further passes
+  if (a.nb <= 1) return launch_nbc<TT, 1, 1>(a, s);
+  if (a.nb <= 2) return launch_nbc<TT, 2, 1>(a, s);
+  if (a.nb <= 4) return launch_nbc<TT, 4, 1>(a, s);
+  if (a.nb <= 8) return launch_nbc<TT, 4, 2>(a, s);
+  return launch_nbc<TT, 4, 4>(a, s);
+}
+
+// dst[g][x'][r] = src[x'][g][r] (r < 2 nL), narrowed to complex64 if TT is.
+template <typename TT>
+__global__ void cap_reorder_kernel(const double2* __restrict__ src, TT* __restrict__ dst, int G, int nL) {
+  const int64_t rows = 2 * (int64_t)nL;
+  const int64_t i = (int64_t)blockIdx.x * kCapThreads + threadIdx.x;
+  if (i >= (int64_t)G * nL * rows) return;
+  const int64_t r = i % rows, xg = i / rows;  // xg = g * nL + x'
+  const int64_t xp = xg % nL, g = xg / nL;
+  dst[i] = from_d2<TT>(src[(xp * G + g) * rows + r]);
 }
 
 }  // namespace
 
 hipError_t launch_cap_apply(const CapArgs& a, hipStream_t s) {
   if (a.nb < 1 || a.G < 1 || a.nL < 1 || !a.T0 || !a.T1 || !a.in || !a.out) return hipErrorInvalidValue;
-  // TN right-hand sides per wave (the smallest power of two covering nb, at
-  // most 4) and RG waves sharing rows: up to 16 right-hand sides per pass
-  // over the table, more in further passes
-  if (a.nb <= 1) return launch_nbc<1, 1>(a, s);
-  if (a.nb <= 2) return launch_nbc<2, 1>(a, s);
-  if (a.nb <= 4) return launch_nbc<4, 1>(a, s);
-  if (a.nb <= 8) return launch_nbc<4, 2>(a, s);
-  return launch_nbc<4, 4>(a, s);
+  return a.t_fp32 ? launch_typed<float2>(a, s) : launch_typed<double2>(a, s);
+}
+
+hipError_t launch_cap_reorder(const double2* src, void* dst, int G, int nL, bool fp32, hipStream_t s) {
+  const int64_t n = (int64_t)G * nL * 2 * nL;
+  const int64_t blocks = (n + kCapThreads - 1) / kCapThreads;
+  if (n <= 0) return hipSuccess;
+  if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+  if (fp32)
+    hipLaunchKernelGGL(cap_reorder_kernel<float2>, dim3((unsigned)blocks), dim3(kCapThreads), 0, s, src,
+                       reinterpret_cast<float2*>(dst), G, nL);
+  else
+    hipLaunchKernelGGL(cap_reorder_kernel<double2>, dim3((unsigned)blocks), dim3(kCapThreads), 0, s, src,
+                       reinterpret_cast<double2*>(dst), G, nL);
+  return hipGetLastError();
 }
 
 }  // namespace helm

@@ -173,6 +173,9 @@ struct LineArgs {
   // the right-hand side e_b (b < nL), so that reductions of the solutions
   // assemble columns of reduced inverses (the boundary operator tables).
   int unit_rhs = 0;
+  // Storing launches (red == 0): blocks take tiles of tile_l outer x tile_m
+  // inner modes of one right-hand side (0: consecutive lines, `tile` each).
+  int tile_l = 0, tile_m = 0;
 };
 
 hipError_t launch_lines(LineArgs a, hipStream_t s);
@@ -188,14 +191,16 @@ hipError_t launch_line_factors(const LineArgs& a, double2* piv, hipStream_t s);
 // Boundary operator tables (cap.hip): for every group g < G (an outer or an
 // inner mode), the reduced inverse of that group's line matrices acting on
 // two boundary vectors,
-//   out[b][g][k][x] = sum_{k' < 2} sum_{x' < nL} T_{k'}[x'][g][k][x] in[b][g][k'][x'],
-// with T_{k'} stored [nL (x')][G][2 (k)][nL (x)] and the vectors addressed by
-// b * _b + g * _g + k * _k + x strides.
+//   out[b][g][k][x] = sum_{k' < 2} sum_{x' < nL} T_{k'}[g][x'][k][x] in[b][g][k'][x'],
+// with T_{k'} stored [G][nL (x')][2 (k)][nL (x)] (complex128, or complex64
+// when t_fp32) and the vectors addressed by b * _b + g * _g + k * _k + x
+// strides; accumulated in FP64.
 // ---------------------------------------------------------------------------
 struct CapArgs {
   int nb = 0, G = 0, nL = 0;
-  const double2* T0 = nullptr;
-  const double2* T1 = nullptr;
+  const void* T0 = nullptr;
+  const void* T1 = nullptr;
+  int t_fp32 = 0;
   const double2* in = nullptr;
   int64_t in_b = 0, in_g = 0, in_k = 0;
   double2* out = nullptr;
@@ -203,6 +208,10 @@ struct CapArgs {
   const int* skip = nullptr;
 };
 hipError_t launch_cap_apply(const CapArgs& a, hipStream_t s);
+// dst[g][x'][k][x] = src[x'][g][k][x] (G groups, 2 nL rows), narrowed to
+// complex64 when fp32: the layout the line reductions produce -> the one the
+// products stream.
+hipError_t launch_cap_reorder(const double2* src, void* dst, int G, int nL, bool fp32, hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // Dense eigenvector transforms on the matrix cores (dense.hip)

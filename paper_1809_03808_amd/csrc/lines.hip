@@ -254,6 +254,7 @@ __device__ inline Aff scan_bwd(Aff v, int q, Aff* wbuf) {
 
 struct LineDev {
   int nb, nO, nI, nL, c, red, tile, ntiles, iters;
+  int tl, tm;  // red == 0 with tm > 0: blocks take tiles of tl outer x tm inner modes
   const double2* sO;
   const double2* sI;
   double2 sC;
@@ -335,6 +336,16 @@ __device__ inline bool decode_line(const LineDev& a, uint32_t g, uint32_t t, int
     m = (g - b * nmg) * (uint32_t)lpb + (uint32_t)sl;
     l = li;
     valid = li < nO && m < nI;
+  } else if (a.tm > 0) {   // tile t = (b, lt, mt), li - t*tile = (l - lt*tl)*tm + (m - mt*tm)
+    const uint32_t nlt = (nO + (uint32_t)a.tl - 1) / (uint32_t)a.tl, nmt = (nI + (uint32_t)a.tm - 1) / (uint32_t)a.tm;
+    const uint32_t idx = li - t * (uint32_t)a.tile;
+    const uint32_t bt = t / nmt, mt = t - bt * nmt;
+    b = bt / nlt;
+    const uint32_t lt = bt - b * nlt;
+    const uint32_t il = idx / (uint32_t)a.tm;
+    l = lt * (uint32_t)a.tl + il;
+    m = mt * (uint32_t)a.tm + (idx - il * (uint32_t)a.tm);
+    valid = idx < (uint32_t)a.tile && l < nO && m < nI && b < (uint32_t)a.nb;
   } else {                 // li = (b*nO + l)*nI + m
     valid = li < (uint32_t)a.nb * nO * nI;
     const uint32_t bl = li / nI;
@@ -923,6 +934,7 @@ LineDev make_dev(const LineArgs& a, int P, int c) {
   d.skip = a.skip;
   d.unit_rhs = a.unit_rhs;
   d.tile = d.ntiles = d.iters = 0;
+  d.tl = d.tm = 0;
   (void)P;
   return d;
 }
@@ -979,6 +991,17 @@ hipError_t launch_lines(LineArgs a, hipStream_t s) {
     d.ntiles = (int)((extent + a.tile - 1) / a.tile);
     if (d.ntiles != a.ntiles) return hipErrorInvalidValue;
     blocks = groups * d.ntiles;
+  } else if (a.tile_m > 0) {
+    // storing launches over (outer, inner) mode tiles: the rank-2 rows of an
+    // inner mode (PO) are then read again only once per outer tile, those of
+    // an outer mode (PI) once per inner tile
+    d.tl = a.tile_l;
+    d.tm = a.tile_m;
+    d.tile = a.tile_l * a.tile_m;
+    const int64_t nt = (int64_t)a.nb * ((a.nO + a.tile_l - 1) / a.tile_l) * ((a.nI + a.tile_m - 1) / a.tile_m);
+    if (nt > 0x7fffffffLL) return hipErrorInvalidValue;
+    d.ntiles = (int)nt;
+    blocks = nt;
   } else {
     const int64_t lines = (int64_t)a.nb * a.nO * a.nI;
     d.tile = a.tile;

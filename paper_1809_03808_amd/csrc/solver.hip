@@ -135,10 +135,11 @@ struct helm_plan {
   // Boundary operator tables (3D, helm_options.boundary): capW holds the
   // inner Step-2 map of every outer periodic mode l (line family (B, A)),
   // capH the outer Step-2 map of every inner absorbing mode m (family
-  // (A, A)); each as two blocks T_{k'}[x'][g][k][x] (cap.hip).  Solves of at
+  // (A, A)); each as two blocks T_{k'}[g][x'][k][x] (cap.hip).  Solves of at
   // least cap_min_nb right-hand sides use them (0: never).
   helm::DevMem capW, capH;
-  const double2 *capW0 = nullptr, *capW1 = nullptr, *capH0 = nullptr, *capH1 = nullptr;
+  const void *capW0 = nullptr, *capW1 = nullptr, *capH0 = nullptr, *capH1 = nullptr;
+  int cap_fp32 = 0;  // tables in complex64 (mixed-precision plans)
   int cap_min_nb = 0;
   double cap_ms[4] = {-1, -1, -1, -1};  // measured: lines at 1 and 16 RHS, tables at 1 and 16 RHS
   std::string tune_path;
@@ -786,7 +787,7 @@ struct InnerIO {
 
 // Product of a boundary operator table with nb pairs of boundary vectors
 // (cap.hip), timed with the table bytes it streams.
-int cap_apply(helm_plan* p, const double2* T0, const double2* T1, int nb, int G, const double2* in,
+int cap_apply(helm_plan* p, const void* T0, const void* T1, int nb, int G, const double2* in,
               int64_t in_b, int64_t in_g, int64_t in_k, double2* out, int64_t out_b, int64_t out_g, int64_t out_k,
               hipStream_t st) {
   CapArgs ca;
@@ -795,6 +796,7 @@ int cap_apply(helm_plan* p, const double2* T0, const double2* T1, int nb, int G,
   ca.nL = p->nL;
   ca.T0 = T0;
   ca.T1 = T1;
+  ca.t_fp32 = p->cap_fp32;
   ca.in = in;
   ca.in_b = in_b;
   ca.in_g = in_g;
@@ -804,7 +806,8 @@ int cap_apply(helm_plan* p, const double2* T0, const double2* T1, int nb, int G,
   ca.out_g = out_g;
   ca.out_k = out_k;
   ca.skip = p->skip_cur;
-  const double by = 2.0 * G * (2.0 * p->nL) * p->nL * sizeof(double2) * ((nb + 15) / 16);
+  const double by = 2.0 * G * (2.0 * p->nL) * p->nL * (p->cap_fp32 ? sizeof(float2) : sizeof(double2)) *
+                    ((nb + 15) / 16);
   HCHK(timed(p, K_CAP, by, st, [&] { return launch_cap_apply(ca, st); }));
   return HELM_OK;
 }
@@ -922,6 +925,13 @@ int inner_solve(helm_plan* p, const Level& lv, const InnerIO& io, hipStream_t st
     s3.out_kind = io.out_kind;
     s3.tile = tl;
     s3.ntiles = ntl;
+    if (lv.nO >= 32 && lv.nI >= 32 && io.PO) {
+      // 32 x 32 mode tiles: the rank-2 rows of either kind are re-read 1/32
+      // as often as with runs of consecutive inner modes
+      int P, c, NT;
+      lines_geometry(lv.nL, &P, &c, &NT);
+      if ((32 * 32) % (NT / P) == 0) s3.tile_l = s3.tile_m = 32;
+    }
   }
   const double by3 = (io.in ? elems * esz_of(io.in_kind) : 0.0) + (io.out ? elems * esz_of(io.out_kind) : 0.0);
   HCHK(timed(p, K_LINES, by3, st, [&] { return launch_lines(s3, st); }));
@@ -1829,14 +1839,16 @@ int build_boundary_tables(helm_plan* p) {
   const double2* c = wt.as<double2>();        // c00, c01, c11 over m
   const double2* dd = c + 3 * (size_t)n2;     // d00, d01, d11 over l
   const size_t blkW = (size_t)nL * n1 * 2 * nL, blkH = (size_t)nL * n2 * 2 * nL;
-  HCHK(p->capW.ensure(2 * blkW * sizeof(double2)));
-  HCHK(p->capH.ensure(2 * blkH * sizeof(double2)));
-  p->capW0 = p->capW.as<double2>();
-  p->capW1 = p->capW0 + blkW;
-  p->capH0 = p->capH.as<double2>();
-  p->capH1 = p->capH0 + blkH;
-  DevMem part;
+  const size_t esz = p->cap_fp32 ? sizeof(float2) : sizeof(double2);
+  HCHK(p->capW.ensure(2 * blkW * esz));
+  HCHK(p->capH.ensure(2 * blkH * esz));
+  p->capW0 = p->capW.p;
+  p->capW1 = static_cast<char*>(p->capW.p) + blkW * esz;
+  p->capH0 = p->capH.p;
+  p->capH1 = static_cast<char*>(p->capH.p) + blkH * esz;
+  DevMem part, stage;  // line partials; one table block in the reductions' layout
   HCHK(part.ensure(std::max(part_elems(1, nL, n1, n2, nL), part_elems(2, nL, n1, n2, nL)) * sizeof(double2)));
+  HCHK(stage.ensure(std::max(blkW, blkH) * sizeof(double2)));
   LineArgs base;
   base.nb = nL;
   base.nO = n1;
@@ -1856,8 +1868,9 @@ int build_boundary_tables(helm_plan* p) {
     la.rho1 = kp ? c + 2 * n2 : c + n2;
     tiles_for(1, nL, n1, n2, nL, &la.tile, &la.ntiles);
     HCHK(launch_lines(la, nullptr));
-    HCHK(launch_sum_partials(base.part, nL * n1, la.ntiles, nL, const_cast<double2*>(kp ? p->capW1 : p->capW0),
-                             nullptr, nullptr));
+    HCHK(launch_sum_partials(base.part, nL * n1, la.ntiles, nL, stage.as<double2>(), nullptr, nullptr));
+    HCHK(launch_cap_reorder(stage.as<double2>(), const_cast<void*>(kp ? p->capW1 : p->capW0), n1, nL,
+                            p->cap_fp32 != 0, nullptr));
   }
   for (int kp = 0; kp < 2; ++kp) {
     LineArgs la = base;  // H: lines of the (A, A) family, reduced over l
@@ -1868,8 +1881,9 @@ int build_boundary_tables(helm_plan* p) {
     la.rho1 = kp ? dd + 2 * n1 : dd + n1;
     tiles_for(2, nL, n1, n2, nL, &la.tile, &la.ntiles);
     HCHK(launch_lines(la, nullptr));
-    HCHK(launch_sum_partials(base.part, nL * n2, la.ntiles, nL, const_cast<double2*>(kp ? p->capH1 : p->capH0),
-                             nullptr, nullptr));
+    HCHK(launch_sum_partials(base.part, nL * n2, la.ntiles, nL, stage.as<double2>(), nullptr, nullptr));
+    HCHK(launch_cap_reorder(stage.as<double2>(), const_cast<void*>(kp ? p->capH1 : p->capH0), n2, nL,
+                            p->cap_fp32 != 0, nullptr));
   }
   HCHK(hipDeviceSynchronize());
   return HELM_OK;
@@ -1961,7 +1975,7 @@ int setup_boundary_tables(helm_plan* p) {
   const bool forced = p->opt.boundary == HELM_BOUNDARY_TABLES;
   const int n1 = p->ax[0].n, n2 = p->ax[1].n, nL = p->nL;
   if ((int64_t)nL * n1 * n2 >= 0x7fffffffLL) return forced ? HELM_EUNSUPPORTED : HELM_OK;
-  const double bytes = 64.0 * nL * nL * (double)(n1 + n2);
+  const double bytes = (p->opt.precision == HELM_PREC_MIXED ? 32.0 : 64.0) * nL * nL * (double)(n1 + n2);
   size_t fr = 0, tot = 0;
   if (hipMemGetInfo(&fr, &tot) != hipSuccess) return HELM_EDEVICE;
   const double budget = std::min(32.0 * (double)(1ull << 30), 0.25 * (double)fr);
@@ -1971,6 +1985,9 @@ int setup_boundary_tables(helm_plan* p) {
   if (!forced && !p->tune_path.empty() && tune_lookup(p->tune_path, key, "boundary cap_min_nb=", &cached) &&
       cached == 0)
     return HELM_OK;  // measured before: the tables never pay for this shape
+  // the mixed-precision path keeps its tables in complex64, like its other
+  // bulk data (they are applied to FP64 boundary vectors with FP64 sums)
+  p->cap_fp32 = p->opt.precision == HELM_PREC_MIXED;
   int rc = build_boundary_tables(p);
   if (rc) return rc;
   if (forced) {

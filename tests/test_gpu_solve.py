@@ -190,6 +190,11 @@ CASES_3D = [
     ((3, 257, 5), 40.0, 0b111111),  # x2 chirp length 576 = 64 x 9
     ((3, 512, 5), 150.0, 0b111111),  # one 512-point pass along x2
     ((3, 3, 513), 150.0, 0b111111),  # lines of 8 x 64 + 1 rows
+    # at least 32 modes on both periodised axes: the storing line launch
+    # takes 32 x 32 mode tiles (ragged at the edges here)
+    ((33, 33, 17), 12.0, 0b111111),
+    ((40, 36, 9), 14.0, 0b110111),
+    ((64, 32, 16), 20.0, 0b111111),
 ]
 
 
@@ -305,6 +310,7 @@ TABLE_CASES = [
     ((3, 4, 512), 150.0, 0b111111, 4),  # exact 64-lane lines
     ((3, 3, 513), 150.0, 0b111111, 2),  # 8 P + 1 rows
     ((6, 5, 300), 30.0, 0b111111, 17),  # padded lines; more than 16 right-hand sides
+    ((33, 40, 9), 14.0, 0b111111, 3),   # mode-tiled storing launch
 ]
 
 
