@@ -23,12 +23,13 @@
  *   - stream is a hipStream_t or NULL for the default stream.
  *   - Every function returns a status code (HELM_OK = 0, negative on error);
  *     no C++ exception crosses this boundary.
- *   - Environment: HELM_RED_L_LAYOUT=3 makes the 3D line solves that reduce
- *     over the x_1 modes give each thread block consecutive x_2 modes at one
- *     x_1 mode instead of one x_2 mode over many x_1 modes (2, the default).
- *     Both give the same sums; the variable exists for testing and tuning
- *     and is read whenever a solve is enqueued (a solve replayed from a
- *     captured graph keeps the layout it was captured with).
+ *   - Tuning: a 3D plan times, at setup, the two block layouts of the line
+ *     solves that reduce over the x_1 modes (each block one x_2 mode over
+ *     many x_1 modes, or consecutive x_2 modes at one x_1 mode; both give
+ *     the same sums) and keeps the faster; HELM_RED_L_LAYOUT=2 or 3 in the
+ *     environment at setup fixes the choice instead (tests).  With
+ *     helm_options.tune_cache set, this and the other measured choices
+ *     (transform, boundary tables) are read from / appended to that file.
  */
 #ifndef HELM_H
 #define HELM_H

@@ -141,6 +141,7 @@ struct helm_plan {
   const void *capW0 = nullptr, *capW1 = nullptr, *capH0 = nullptr, *capH1 = nullptr;
   int cap_fp32 = 0;  // tables in complex64 (mixed-precision plans)
   int cap_min_nb = 0;
+  int red_layout = 2;  // layout of the line reductions over the outer modes (2 or 3)
   double cap_ms[4] = {-1, -1, -1, -1};  // measured: lines at 1 and 16 RHS, tables at 1 and 16 RHS
   std::string tune_path;
   double tune_ms[2] = {-1.0, -1.0};  // measured FFT / dense solve times (AUTO)
@@ -697,19 +698,14 @@ int run_fft(helm_plan* p, const PAxis& a, int sign, bool fp32, const void* in, i
   return HELM_OK;
 }
 
-// Layout of a reduction over l (red 2 or 3, see the line kernel).  Red 2
-// (one m per block, slots over l) is the default for every size: red 3
-// (slots over consecutive m at one l) measured 0.5% slower at 512^3 x 16,
-// 1.5% slower at 256^3 and 1% faster at 513^3.  HELM_RED_L_LAYOUT=2 or 3 in
-// the environment selects one (both compute the same sums).
-int red_l_mode(int nb, int nI, int nL) {
-  (void)nb;
-  (void)nI;
-  (void)nL;
-  const char* env = std::getenv("HELM_RED_L_LAYOUT");
-  if (env && env[0] == '3' && env[1] == 0) return 3;
-  return 2;
-}
+// Layout of a reduction over l (red 2 or 3, see the line kernel): red 2
+// gives a block one m and its slots consecutive l, red 3 gives the slots
+// consecutive m at one l.  Both compute the same sums; which is faster
+// depends on the shape (measured at 512^3 x 16: red 3 0.5% slower, at 256^3
+// 1.5% slower, at 513^3 1% faster), so the plan times both at setup (3D) and
+// keeps the faster (tune_layout); HELM_RED_L_LAYOUT=2 or 3 in the
+// environment at setup fixes it instead (tests).
+int red_l_mode(const helm_plan* p) { return p->red_layout; }
 
 // Lines per tile and tiles of a line launch; `layout` (2 or 3) only matters
 // for red 2.  At least 8 lines feed each partial sum (partials stay below 1/4
@@ -744,8 +740,8 @@ void tiles_for_layout(int red, int layout, int nb, int nO, int nI, int nL, int* 
   *ntiles = (int)((extent + t - 1) / t);
 }
 
-void tiles_for(int red, int nb, int nO, int nI, int nL, int* tile, int* ntiles) {
-  tiles_for_layout(red, red == 2 ? red_l_mode(nb, nI, nL) : red, nb, nO, nI, nL, tile, ntiles);
+void tiles_for(const helm_plan* p, int red, int nb, int nO, int nI, int nL, int* tile, int* ntiles) {
+  tiles_for_layout(red, red == 2 ? red_l_mode(p) : red, nb, nO, nI, nL, tile, ntiles);
 }
 
 // Partial sums of a reducing launch; for red 2 the larger of the two layouts,
@@ -831,7 +827,7 @@ int inner_solve(helm_plan* p, const Level& lv, const InnerIO& io, hipStream_t st
   double2* part = p->part.as<double2>();
   const double elems = (double)lv.nb * lv.nO * lv.nI * lv.nL;
   int tile, nt;
-  tiles_for(1, lv.nb, lv.nO, lv.nI, lv.nL, &tile, &nt);
+  tiles_for(p, 1, lv.nb, lv.nO, lv.nI, lv.nL, &tile, &nt);
 
   // S1: (T^B)^{-1} of the right-hand side, reduced to the two boundary rows.
   LineArgs s1 = base;
@@ -911,8 +907,8 @@ int inner_solve(helm_plan* p, const Level& lv, const InnerIO& io, hipStream_t st
   s3.beta1 = I.genB1;
   if (io.rhoL0) {
     int tl, ntl;
-    tiles_for(2, lv.nb, lv.nO, lv.nI, lv.nL, &tl, &ntl);
-    s3.red = red_l_mode(lv.nb, lv.nI, lv.nL);
+    tiles_for(p, 2, lv.nb, lv.nO, lv.nI, lv.nL, &tl, &ntl);
+    s3.red = red_l_mode(p);
     s3.rho0 = io.rhoL0;
     s3.rho1 = io.rhoL1;
     s3.part = part;
@@ -920,7 +916,7 @@ int inner_solve(helm_plan* p, const Level& lv, const InnerIO& io, hipStream_t st
     s3.ntiles = ntl;
   } else {
     int tl, ntl;
-    tiles_for(0, lv.nb, lv.nO, lv.nI, lv.nL, &tl, &ntl);
+    tiles_for(p, 0, lv.nb, lv.nO, lv.nI, lv.nL, &tl, &ntl);
     s3.out = io.out;
     s3.out_kind = io.out_kind;
     s3.tile = tl;
@@ -957,7 +953,7 @@ __global__ void sum_to_planes_kernel(const double2* __restrict__ part, int nb, i
 
 int sum_to_planes(helm_plan* p, const Level& lv, double2* out, hipStream_t st) {
   int tl, ntl;
-  tiles_for(2, lv.nb, lv.nO, lv.nI, lv.nL, &tl, &ntl);
+  tiles_for(p, 2, lv.nb, lv.nO, lv.nI, lv.nL, &tl, &ntl);
   const int64_t total = (int64_t)lv.nb * 2 * lv.nI * lv.nL;
   HCHK(timed(p, K_SUM, (double)total * sizeof(double2) * (ntl + 1), st, [&] {
     hipLaunchKernelGGL(sum_to_planes_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st,
@@ -1017,7 +1013,7 @@ int solve_dense(helm_plan* p, const void* x, int x_kind, double2* u, int accumul
     la.in = W0;
     la.out = W0;
     la.tile = 0;
-    tiles_for(0, nb, 1, n1, n2, &la.tile, &la.ntiles);
+    tiles_for(p, 0, nb, 1, n1, n2, &la.tile, &la.ntiles);
     HCHK(timed(p, K_LINES, (double)nb * n1 * n2 * 2 * esz_of(T), st, [&] { return launch_lines(la, st); }));
     return dense_pass(p, n1, n2, nb, inv(A1), W0, T, u, ST_C128, accumulate, fp32, st);
   }
@@ -1033,7 +1029,7 @@ int solve_dense(helm_plan* p, const void* x, int x_kind, double2* u, int accumul
   la.piv = p->seed[3];
   la.in = W1;
   la.out = W1;
-  tiles_for(0, nb, n1, n2, n3, &la.tile, &la.ntiles);
+  tiles_for(p, 0, nb, n1, n2, n3, &la.tile, &la.ntiles);
   HCHK(timed(p, K_LINES, (double)nb * n1 * n2 * n3 * 2 * esz_of(T), st, [&] { return launch_lines(la, st); }));
   rc = dense_pass(p, n2, n3, (int64_t)nb * n1, inv(A2), W1, T, W0, T, 0, fp32, st);
   if (rc) return rc;
@@ -1866,7 +1862,7 @@ int build_boundary_tables(helm_plan* p) {
     la.red = 1;
     la.rho0 = kp ? c + n2 : c;
     la.rho1 = kp ? c + 2 * n2 : c + n2;
-    tiles_for(1, nL, n1, n2, nL, &la.tile, &la.ntiles);
+    tiles_for(p, 1, nL, n1, n2, nL, &la.tile, &la.ntiles);
     HCHK(launch_lines(la, nullptr));
     HCHK(launch_sum_partials(base.part, nL * n1, la.ntiles, nL, stage.as<double2>(), nullptr, nullptr));
     HCHK(launch_cap_reorder(stage.as<double2>(), const_cast<void*>(kp ? p->capW1 : p->capW0), n1, nL,
@@ -1876,10 +1872,10 @@ int build_boundary_tables(helm_plan* p) {
     LineArgs la = base;  // H: lines of the (A, A) family, reduced over l
     la.sTab = p->sig[3];
     la.piv = p->seed[3];
-    la.red = red_l_mode(nL, n2, nL);
+    la.red = red_l_mode(p);
     la.rho0 = kp ? dd + n1 : dd;
     la.rho1 = kp ? dd + 2 * n1 : dd + n1;
-    tiles_for(2, nL, n1, n2, nL, &la.tile, &la.ntiles);
+    tiles_for(p, 2, nL, n1, n2, nL, &la.tile, &la.ntiles);
     HCHK(launch_lines(la, nullptr));
     HCHK(launch_sum_partials(base.part, nL * n2, la.ntiles, nL, stage.as<double2>(), nullptr, nullptr));
     HCHK(launch_cap_reorder(stage.as<double2>(), const_cast<void*>(kp ? p->capH1 : p->capH0), n2, nL,
@@ -1921,7 +1917,7 @@ int measure_boundary(helm_plan* p, int nb, double* t_lines, double* t_tab) {
   s2.rho0 = A2.va0d;
   s2.rho1 = A2.va1d;
   s2.part = part.as<double2>();
-  tiles_for(1, nb, n1, n2, nL, &s2.tile, &s2.ntiles);
+  tiles_for(p, 1, nb, n1, n2, nL, &s2.tile, &s2.ntiles);
   auto lines = [&]() -> int {
     HCHK(launch_lines(s2, nullptr));
     return HELM_OK;
@@ -1967,6 +1963,89 @@ int measure_boundary(helm_plan* p, int nb, double* t_lines, double* t_tab) {
   *t_lines = 5.0 * best[0];
   *t_tab = best[1];
   return rc;
+}
+
+// Layout of the line reductions over the outer modes (3D): fixed by
+// HELM_RED_L_LAYOUT (2 or 3) when set, else the cached decision, else the
+// faster of the two on an outer-Step-1 sweep of one right-hand side (read of
+// an N-sized input, generated rank-2 term, weighted sums over l; best of 3
+// after a warm-up), appended to the cache.
+int tune_layout(helm_plan* p) {
+  const char* env = std::getenv("HELM_RED_L_LAYOUT");
+  if (env && (env[0] == '2' || env[0] == '3') && env[1] == 0) {
+    p->red_layout = env[0] - '0';
+    return HELM_OK;
+  }
+  const std::string key = tune_key(p);
+  int cached = 0;
+  if (!p->tune_path.empty() && tune_lookup(p->tune_path, key, "layout=", &cached) && (cached == 2 || cached == 3)) {
+    p->red_layout = cached;
+    return HELM_OK;
+  }
+  const PAxis& A1 = p->ax[0];
+  const PAxis& A2 = p->ax[1];
+  const int n1 = A1.n, n2 = A2.n, nL = p->nL;
+  const bool fp32 = p->opt.precision == HELM_PREC_MIXED;
+  const size_t esz = fp32 ? sizeof(float2) : sizeof(double2);
+  DevMem in, pi, part;
+  HCHK(in.ensure((size_t)n1 * n2 * nL * esz));
+  HCHK(pi.ensure((size_t)n1 * 2 * nL * sizeof(double2)));
+  HCHK(part.ensure(part_elems(2, 1, n1, n2, nL) * sizeof(double2)));
+  HCHK(hipMemset(in.p, 0x3f, in.bytes));  // finite values of order 1e-3 (1 in complex64)
+  HCHK(hipMemset(pi.p, 0x3f, pi.bytes));
+  LineArgs la;
+  la.nb = 1;
+  la.nO = n1;
+  la.nI = n2;
+  la.nL = nL;
+  la.hL = p->hL;
+  la.kLo = p->kLo;
+  la.kHi = p->kHi;
+  la.sTab = p->sig[0];
+  la.piv = p->seed[0];
+  la.in = in.p;
+  la.in_kind = fp32 ? ST_C64 : ST_C128;
+  la.PI = pi.as<double2>();
+  la.beta0 = A2.genB0;
+  la.beta1 = A2.genB1;
+  la.rho0 = A1.redB0;
+  la.rho1 = A1.redB1;
+  la.part = part.as<double2>();
+  hipEvent_t e0, e1;
+  HCHK(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return HELM_EDEVICE;
+  }
+  int rc = HELM_OK;
+  double best[2] = {1e30, 1e30};
+  for (int v = 0; v < 2 && !rc; ++v) {
+    la.red = 2 + v;
+    tiles_for_layout(2, la.red, 1, n1, n2, nL, &la.tile, &la.ntiles);
+    for (int rep = 0; rep < 4 && !rc; ++rep) {
+      float ms = 0;
+      if (hipEventRecord(e0, nullptr) != hipSuccess || launch_lines(la, nullptr) != hipSuccess ||
+          hipEventRecord(e1, nullptr) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+          hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+        rc = HELM_EDEVICE;
+        break;
+      }
+      if (rep > 0) best[v] = std::min(best[v], (double)ms);
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc) return rc;
+  p->red_layout = best[1] < best[0] ? 3 : 2;
+  if (!p->tune_path.empty()) {
+    FILE* f = std::fopen(p->tune_path.c_str(), "a");
+    if (f) {
+      std::fprintf(f, "helm-tune %s layout=%d layout2_ms=%.6g layout3_ms=%.6g\n", key.c_str(), p->red_layout,
+                   best[0], best[1]);
+      std::fclose(f);
+    }
+  }
+  return HELM_OK;
 }
 
 // Builds the tables when they fit the budget and decides from which number
@@ -2296,6 +2375,10 @@ int helm_setup(int dim, const int64_t* grid, const double* h, double omega, uint
       p->seed[k] = dst;
     }
     if (hipDeviceSynchronize() != hipSuccess) return HELM_EDEVICE;
+  }
+  if (dim == 3 && tf != HELM_TRANSFORM_DENSE) {
+    const int lrc = tune_layout(p.get());
+    if (lrc != HELM_OK) return lrc;
   }
   if (want_tab) {
     const int brc = setup_boundary_tables(p.get());

@@ -126,3 +126,31 @@ def test_batch_of_dense_and_fft_plans():
     batch.close()
     for p in plans:
         p.close()
+
+
+def test_cached_schedule_decisions_are_honoured(tmp_path):
+    """Decisions read from the tune cache (3D: boundary tables from one
+    right-hand side on, reductions over the outer modes in layout 3; or
+    never the tables) are what the plan runs, and the results meet the bar."""
+    grid, omega = (12, 10, 9), 8.0
+    h = inputs.spacing(grid)
+    f = inputs.gaussian_batch(grid, [97, 98])
+    ref = fem.solve(grid, h, omega, ((True, True),) * 3, f.reshape(2, -1))
+    for prec in (helm.PREC_FP64, helm.PREC_MIXED):
+        key = f"dim=3 grid={grid[0]}x{grid[1]}x{grid[2]} prec={prec}"
+        for nmin, want in ((1, helm.BOUNDARY_TABLES), (0, helm.BOUNDARY_LINES)):
+            cache = tmp_path / f"tune_{prec}_{nmin}.txt"
+            cache.write_text(f"helm-tune {key} layout=3 layout2_ms=1 layout3_ms=0.5\n"
+                             f"helm-tune {key} boundary cap_min_nb={nmin}\n")
+            with helm.Plan(grid, h, omega, precision=prec, check=prec == helm.PREC_MIXED,
+                           tune_cache=str(cache)) as plan:
+                fd = torch.from_numpy(f).cuda()
+                ud = torch.empty_like(fd)
+                plan.solve(fd, ud)
+                rep = plan.report()
+                u = ud.cpu().numpy().reshape(2, -1)
+            err = fem.rel_error(u, ref)
+            assert rep["boundary"] == want, (prec, nmin, rep)
+            assert np.max(err) <= (1e-9 if prec == helm.PREC_FP64 else 1e-8)
+            # nothing was measured, so nothing was appended
+            assert len(cache.read_text().splitlines()) == 2
