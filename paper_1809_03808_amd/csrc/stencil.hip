@@ -286,11 +286,12 @@ __global__ __launch_bounds__(k3Threads) void residual3d_kernel(ResidArgs a, int6
   const AxisOp& A2 = a.ax[1];
   const AxisOp& A3 = a.ax[2];
   const int n1 = A1.n, n2 = A2.n, n3 = A3.n;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);  // wave-uniform
   const int x = (int)xi * 64 + lane;
   const bool xok = x < n3;
   const int y0 = (int)yi * k3Rows;      // first output row (x_2) of the tile
-  const int y = y0 + wv;                // this thread's output row
+  const int y = y0 + wv;                // this wave's output row
   const bool yok = y < n2;
   const int r0 = (int)si * kStrip, r1 = min(n1, r0 + kStrip);
   const int64_t plane = (int64_t)n2 * n3;
@@ -298,56 +299,77 @@ __global__ __launch_bounds__(k3Threads) void residual3d_kernel(ResidArgs a, int6
   const double2* U = a.u + off;
   const int xe = lane == 0 ? x - 1 : x + 1;
   const bool edge = (lane == 0 || lane == 63) && xe >= 0 && xe < n3;
-  const double m3L = m1d(n3, A3.h, x, -1), m3C = m1d(n3, A3.h, x, 0), m3R = m1d(n3, A3.h, x, 1);
-  const double2 k3L = k1d(n3, A3.h, A3.kLo, A3.kHi, x, -1), k3C = k1d(n3, A3.h, A3.kLo, A3.kHi, x, 0),
-                k3R = k1d(n3, A3.h, A3.kLo, A3.kHi, x, 1);
-  // x_2 coefficients of this thread's output row
-  double m2[3];
-  double2 k2[3];
+  // Values outside the domain are loaded as zero, so the off-diagonal
+  // entries can be the interior ones everywhere (uniform); only the
+  // diagonal entries of the end nodes differ: per lane along x_3, per wave
+  // along x_2.
+  const double m3O = A3.h / 6.0, k3O = -1.0 / A3.h;
+  const double m3C = m1d(n3, A3.h, x, 0);
+  const double2 k3C = k1d(n3, A3.h, A3.kLo, A3.kHi, x, 0);
+  const double m2O = yok ? A2.h / 6.0 : 0.0, k2O = yok ? -1.0 / A2.h : 0.0;
+  const double m2C = yok ? m1d(n2, A2.h, y, 0) : 0.0;
+  const double2 k2C = yok ? k1d(n2, A2.h, A2.kLo, A2.kHi, y, 0) : make_double2(0, 0);
+  // The rows y0 - 1 + rr (rr < k3Load) of a plane are loaded by wave
+  // rr % k3Rows: every wave owns row wv, waves 0 and 1 also row wv + k3Rows.
+  // The loads of plane j + 1 are issued before plane j is combined, so a
+  // plane's loads are in flight during the previous plane's LDS work.
+  struct Raw {
+    double2 c[2], e[2];  // u at the lane's column, and the wave-edge neighbour
+  };
+  auto load_plane = [&](int j) {
+    Raw w;
 #pragma unroll
-  for (int o = -1; o <= 1; ++o) {
-    m2[o + 1] = yok ? m1d(n2, A2.h, y, o) : 0.0;
-    k2[o + 1] = yok ? k1d(n2, A2.h, A2.kLo, A2.kHi, y, o) : make_double2(0, 0);
-  }
-  // plane j -> (P, Q) at this thread's point; buffer `buf` of the LDS rows
-  auto plane_op = [&](int j, int buf, double2& P, double2& Q) {
-    // rows y0 - 1 + rr, rr < k3Load, loaded by wave rr % k3Rows
-    for (int rr = wv; rr < k3Load; rr += k3Rows) {
+    for (int t = 0; t < 2; ++t) {
+      const int rr = wv + t * k3Rows;
       const int yy = y0 - 1 + rr;
-      double2 c = make_double2(0, 0), e = make_double2(0, 0);
-      if (j >= 0 && j < n1 && yy >= 0 && yy < n2) {
+      w.c[t] = make_double2(0, 0);
+      w.e[t] = make_double2(0, 0);
+      if (rr < k3Load && j >= 0 && j < n1 && yy >= 0 && yy < n2) {
         const double2* row = U + (int64_t)j * plane + (int64_t)yy * n3;
-        if (xok) c = row[x];
-        if (edge) e = row[xe];
+        if (xok) w.c[t] = row[x];
+        if (edge) w.e[t] = row[xe];
       }
-      double2 l = make_double2(__shfl_up(c.x, 1), __shfl_up(c.y, 1));
-      double2 r = make_double2(__shfl_down(c.x, 1), __shfl_down(c.y, 1));
-      if (lane == 0) l = e;
-      if (lane == 63) r = e;
-      Mx[buf][rr][lane] = make_double2(m3L * l.x + m3C * c.x + m3R * r.x, m3L * l.y + m3C * c.y + m3R * r.y);
-      Kx[buf][rr][lane] = cfma(k3L, l, cfma(k3C, c, cmul(k3R, r)));
+    }
+    return w;
+  };
+  // x_3 operators of the loaded rows into LDS buffer `buf`, then (P, Q) at
+  // this thread's point
+  auto plane_op = [&](const Raw& w, int buf, double2& P, double2& Q) {
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      const int rr = wv + t * k3Rows;
+      if (rr < k3Load) {
+        const double2 c = w.c[t];
+        double2 l = make_double2(__shfl_up(c.x, 1), __shfl_up(c.y, 1));
+        double2 r = make_double2(__shfl_down(c.x, 1), __shfl_down(c.y, 1));
+        if (lane == 0) l = w.e[t];
+        if (lane == 63) r = w.e[t];
+        const double2 lr = cadd(l, r);
+        Mx[buf][rr][lane] = make_double2(fma(m3O, lr.x, m3C * c.x), fma(m3O, lr.y, m3C * c.y));
+        Kx[buf][rr][lane] = cfma(k3C, c, cscale(lr, k3O));
+      }
     }
     __syncthreads();
-    P = make_double2(0, 0);
-    Q = make_double2(0, 0);
-#pragma unroll
-    for (int o = -1; o <= 1; ++o) {
-      const double2 mv = Mx[buf][wv + 1 + o][lane], kv = Kx[buf][wv + 1 + o][lane];
-      P = cadd(P, cscale(mv, m2[o + 1]));
-      Q = cadd(Q, cadd(cmul(k2[o + 1], mv), cscale(kv, m2[o + 1])));
-    }
+    const double2 ms = cadd(Mx[buf][wv][lane], Mx[buf][wv + 2][lane]), mc = Mx[buf][wv + 1][lane];
+    const double2 ks = cadd(Kx[buf][wv][lane], Kx[buf][wv + 2][lane]), kc = Kx[buf][wv + 1][lane];
+    P = make_double2(fma(m2O, ms.x, m2C * mc.x), fma(m2O, ms.y, m2C * mc.y));
+    // (K_2 (x) M_3 + M_2 (x) K_3) u: off-diagonal K_2 and M_2 entries are real
+    Q = cfma(k2C, mc, make_double2(fma(k2O, ms.x, fma(m2O, ks.x, m2C * kc.x)),
+                                   fma(k2O, ms.y, fma(m2O, ks.y, m2C * kc.y))));
   };
   double2 Pp, Qp, Pc, Qc;
-  plane_op(r0 - 1, 0, Pp, Qp);
-  plane_op(r0, 1, Pc, Qc);
+  plane_op(load_plane(r0 - 1), 0, Pp, Qp);
+  plane_op(load_plane(r0), 1, Pc, Qc);
+  Raw nx = load_plane(r0 + 1);
   double sr = 0.0, sf = 0.0;
   int buf = 0;
   for (int i = r0; i < r1; ++i) {
     const bool ok = xok && yok;
     const int64_t idx = off + (int64_t)i * plane + (int64_t)y * n3 + x;
     const double2 fv = ok ? a.f[idx] : make_double2(0, 0);
+    const Raw nn = load_plane(i + 2);  // in flight while plane i + 1 is combined
     double2 Pn, Qn;
-    plane_op(i + 1, buf, Pn, Qn);  // two LDS buffers alternate: the one read last is not overwritten
+    plane_op(nx, buf, Pn, Qn);  // two LDS buffers alternate: the one read last is not overwritten
     buf ^= 1;
     double2 au = make_double2(0, 0);
     const double2* Ps[3] = {&Pp, &Pc, &Pn};
@@ -369,6 +391,7 @@ __global__ __launch_bounds__(k3Threads) void residual3d_kernel(ResidArgs a, int6
     Qp = Qc;
     Pc = Pn;
     Qc = Qn;
+    nx = nn;
   }
   red[0][threadIdx.x] = sr;
   red[1][threadIdx.x] = sf;

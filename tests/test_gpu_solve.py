@@ -272,7 +272,7 @@ def test_mixed_precision_refines_to_1e10(grid, omega):
     assert np.max(err) <= 1e-8
 
 
-@pytest.mark.parametrize("grid", [(16, 11), (8, 8, 5)])
+@pytest.mark.parametrize("grid", [(16, 11), (8, 8, 5), (5, 17, 130), (35, 9, 65), (70, 33, 20)])
 def test_residual_kernel_matches_oracle(grid):
     grid = tuple(grid)
     mask = (1 << (2 * len(grid))) - 1
