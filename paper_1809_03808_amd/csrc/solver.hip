@@ -921,12 +921,16 @@ int inner_solve(helm_plan* p, const Level& lv, const InnerIO& io, hipStream_t st
     s3.out_kind = io.out_kind;
     s3.tile = tl;
     s3.ntiles = ntl;
-    if (lv.nO >= 32 && lv.nI >= 32 && io.PO) {
-      // 32 x 32 mode tiles: the rank-2 rows of either kind are re-read 1/32
-      // as often as with runs of consecutive inner modes
+    if (io.PO) {
+      // square mode tiles of about as many lines as the consecutive runs
+      // would have (so the launch keeps its number of blocks): the rank-2
+      // rows of either kind are then re-read once per tile row / column
+      // instead of once per outer mode
       int P, c, NT;
       lines_geometry(lv.nL, &P, &c, &NT);
-      if ((32 * 32) % (NT / P) == 0) s3.tile_l = s3.tile_m = 32;
+      int e = 32;
+      while (e > 4 && (e * e > tl || e > lv.nO || e > lv.nI)) e /= 2;
+      if (e >= 8 && (e * e) % (NT / P) == 0) s3.tile_l = s3.tile_m = e;
     }
   }
   const double by3 = (io.in ? elems * esz_of(io.in_kind) : 0.0) + (io.out ? elems * esz_of(io.out_kind) : 0.0);
