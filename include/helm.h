@@ -58,7 +58,7 @@ extern "C" {
 
 /* Solver options.  helm_default_options fills: precision = HELM_PREC_FP64,
  * tol = 1e-10, max_iter = 8, check = 1, transform = FFT, tune_cache = NULL,
- * boundary = AUTO. */
+ * boundary = AUTO, eigen = AUTO. */
 /* Transform along the periodised axes (helm_options.transform):
  *   FFT   the fast method of Sections 4.2 / 5.2: DFTs of the periodic
  *         problem, three line passes and the boundary steps;
@@ -97,6 +97,22 @@ extern "C" {
 #define HELM_BOUNDARY_LINES  1
 #define HELM_BOUNDARY_TABLES 2
 
+/* Where the absorbing-boundary eigenpairs of eq. (EVP1a) are computed at setup
+ * (helm_options.eigen; Section 6 notes that this eigen-solve dominates the
+ * initialisation):
+ *   HOST    the host root finder and extended-precision inverse iteration
+ *           (OpenMP; helm_eig1d);
+ *   DEVICE  the same method on the current HIP device, one thread per root
+ *           (Aberth sweeps in FP64, inverse iteration in double-double
+ *           arithmetic; helm_eig1d_device), with the whole eigenvectors, when
+ *           the plan needs them, written straight to device memory;
+ *   AUTO    DEVICE.
+ * Both meet the same acceptance checks (normwise backward error below 1e-12
+ * per pair, distinct eigenvalues); the eigenvalues agree to rounding. */
+#define HELM_EIGEN_AUTO   0
+#define HELM_EIGEN_HOST   1
+#define HELM_EIGEN_DEVICE 2
+
 typedef struct helm_options {
     int    precision; /* HELM_PREC_FP64 or HELM_PREC_MIXED */
     double tol;       /* target ||f - A u||_2 / ||f||_2 per right-hand side */
@@ -107,6 +123,7 @@ typedef struct helm_options {
     int    transform; /* HELM_TRANSFORM_*; default FFT */
     const char* tune_cache; /* AUTO only: decision cache file, or NULL */
     int    boundary;  /* HELM_BOUNDARY_*; default AUTO */
+    int    eigen;     /* HELM_EIGEN_*; default AUTO */
 } helm_options;
 
 void helm_default_options(helm_options* opt);
@@ -128,10 +145,11 @@ typedef struct helm_plan helm_plan;
  *          exactly singular).
  *   opt    options or NULL for the defaults
  *   out    receives the plan
- * Computes the FP64 1D spectra on the host: closed-form periodic spectra
- * (eqs. (eigvectorsPer), (eigvaluesPer)) and the absorbing-boundary
- * generalized eigenpairs K V = M V Lambda^A (eq. (EVP1a), normalised as in
- * eq. (EVPcondA)), then uploads them to the current HIP device.
+ * Computes the 1D spectra: closed-form periodic spectra (eqs. (eigvectorsPer),
+ * (eigvaluesPer)) on the host and the absorbing-boundary generalized
+ * eigenpairs K V = M V Lambda^A (eq. (EVP1a), normalised as in eq. (EVPcondA))
+ * on the current HIP device or the host (helm_options.eigen), and builds the
+ * plan's device tables there.
  * Size limits of this build: the last (line) axis has at most 4097 nodes;
  * a periodised axis of n nodes needs a transform length (n itself for a power
  * of two, else a chirp-z length >= 2n - 1) of at most 2^18.
@@ -142,6 +160,30 @@ typedef struct helm_plan helm_plan;
  */
 int helm_setup(int dim, const int64_t* grid, const double* h, double omega,
                uint32_t abc, const helm_options* opt, helm_plan** out);
+
+/*
+ * helm_setup_general -- the same for the operator with a zeroth-order
+ * coefficient of either sign and Robin (impedance) faces, the other separable
+ * problems of Section 1: -Lap u - c u = f in the box, du/dn + g u = 0 on each
+ * face (outward normal).  The Galerkin matrices are those of eqs. (A2D),
+ * (A3D) with c in place of omega^2 and the corner entries of K_j
+ * (eq. (matrixK)) equal to 1/h_j + g of the face; helm_setup is the case
+ * c = omega^2, g = -i omega on absorbing faces (eq. (1st-order-abc)) and
+ * g = 0 on Neumann faces.
+ *   c      real zeroth-order coefficient (c < 0: modified Helmholtz, c = 0: Laplace)
+ *   gamma  host array of 4 dim doubles: g of the low face of axis j at
+ *          (gamma[4j], gamma[4j+1]) = (Re, Im), of the high face at
+ *          (gamma[4j+2], gamma[4j+3])
+ * Accepted coefficient sets (every line system of the method nonsingular):
+ * some face of the last axis with Im g != 0 and no two faces with Im g of
+ * opposite signs; or every g real and >= 0 with c < 0, or with c = 0 and
+ * g > 0 on a face of the last axis.  Errors as helm_setup: HELM_EINVAL
+ * (non-finite c or g, bad sizes), HELM_ESINGULAR (c = 0 and g = 0 on every
+ * face: A annihilates the constants), HELM_EUNSUPPORTED (other coefficient
+ * sets, where resonant line systems are possible; size limits).
+ */
+int helm_setup_general(int dim, const int64_t* grid, const double* h, double c,
+                       const double* gamma, const helm_options* opt, helm_plan** out);
 
 /*
  * helm_solve -- u = A^{-1} f for nrhs right-hand sides.
@@ -298,6 +340,21 @@ const char* helm_strerror(int code);
  */
 int helm_eig1d(int64_t n, double h, double omega, int abc_lo, int abc_hi,
                double* lam, double* vb);
+
+/*
+ * helm_eig1d_device -- the same eigenpairs, computed on the current HIP device
+ * by the method of HELM_EIGEN_DEVICE (Aberth-Ehrlich sweeps on
+ * det(K - lambda M) in FP64, then inverse iteration per root with the
+ * complex-symmetric Rayleigh quotient in double-double arithmetic, at least
+ * three steps and up to eight until the quotient settles to 1e-26).
+ * Arguments and output layout as helm_eig1d (host arrays; the call
+ * synchronises).  Allocates device memory for its workspace (at most 4 GiB
+ * plus O(n) bytes) and frees it before returning.
+ * Errors: HELM_EINVAL (n < 3 or n > 2^20, h <= 0, non-finite omega, null
+ * arrays), HELM_ENOCONV, HELM_ENOMEM, HELM_EDEVICE.
+ */
+int helm_eig1d_device(int64_t n, double h, double omega, int abc_lo, int abc_hi,
+                      double* lam, double* vb);
 
 #ifdef __cplusplus
 }

@@ -20,7 +20,7 @@ BUILD = os.path.join(ROOT, "_build")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 ARCH = os.environ.get("HELM_OFFLOAD_ARCH", "gfx950")
 
-HIP_SOURCES = ["fft.hip", "lines.hip", "boundary.hip", "stencil.hip", "dense.hip", "cap.hip", "solver.hip"]
+HIP_SOURCES = ["fft.hip", "lines.hip", "boundary.hip", "stencil.hip", "dense.hip", "cap.hip", "eigdev.hip", "solver.hip"]
 CXX_SOURCES = ["eig1d.cpp"]
 
 HIPCC_FLAGS = [

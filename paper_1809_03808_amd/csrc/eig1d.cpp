@@ -1,7 +1,9 @@
 // Host FP64 eigen-setup of the 1D absorbing-boundary pencil.
 //
 // Computes all eigenpairs of K v = lambda M v (eq. (EVP1a)) for the 1D
-// stiffness and mass matrices of eqs. (matrixK), (matrixM), normalised by
+// stiffness and mass matrices of eqs. (matrixK), (matrixM) -- K with corner
+// entries 1/h + g for a face condition du/dn + g u = 0 (absorbing:
+// g = -i omega; Neumann: g = 0; Robin / impedance: any g) -- normalised by
 // v^T M v = 1 (eq. (EVPcondA); plain transpose, the pencil is complex
 // symmetric), and returns the eigenvalues and the two boundary rows of V.
 //
@@ -17,7 +19,7 @@
 //      elimination with partial pivoting on the tridiagonal K - lambda M,
 //      in x87 extended precision with a cancellation-free x^T K x;
 //   3. each eigenvector scaled by (v^T M v)^{-1/2}.
-// With both faces Neumann (or omega = 0) the spectrum is the closed-form
+// With g = 0 on both faces (Neumann) the spectrum is the closed-form
 // cosine one, 6(1 - cos t)/(h^2 (2 + cos t)), t = k pi/(n - 1), used directly
 // as the starting values of step 2.
 #include <algorithm>
@@ -43,13 +45,13 @@ struct Pencil {
   double mb;               // off-diagonal of M (h/6)
 };
 
-Pencil make_pencil(int n, double h, double omega, int lo, int hi) {
+Pencil make_pencil(int n, double h, cd glo, cd ghi) {
   Pencil P;
   P.n = n;
   P.ka.assign(n, cd(2.0 / h, 0.0));
   P.ma.assign(n, 4.0 * h / 6.0);
-  P.ka[0] = lo ? cd(1.0, -omega * h) / h : cd(1.0 / h, 0.0);
-  P.ka[n - 1] = hi ? cd(1.0, -omega * h) / h : cd(1.0 / h, 0.0);
+  P.ka[0] = cd(1.0 / h, 0.0) + glo;
+  P.ka[n - 1] = cd(1.0 / h, 0.0) + ghi;
   P.ma[0] = P.ma[n - 1] = 2.0 * h / 6.0;
   P.kb = -1.0 / h;
   P.mb = h / 6.0;
@@ -125,23 +127,22 @@ void tri_solve_pp(std::vector<xc>& dl, std::vector<xc>& d, std::vector<xc>& du,
 struct XPencil {
   int n;
   xr h, w;
-  int lo, hi;
+  xc glo, ghi;
   std::vector<xc> ka;
   std::vector<xr> ma;
   xr kb, mb;
 };
 
-XPencil make_xpencil(int n, double h, double omega, int lo, int hi) {
+XPencil make_xpencil(int n, double h, cd glo, cd ghi) {
   XPencil P;
   P.n = n;
   P.h = h;
-  P.w = omega;
-  P.lo = lo;
-  P.hi = hi;
+  P.glo = xc(glo.real(), glo.imag());
+  P.ghi = xc(ghi.real(), ghi.imag());
   P.ka.assign(n, xc(2.0L / P.h, 0.0L));
   P.ma.assign(n, 4.0L * P.h / 6.0L);
-  P.ka[0] = xc(1.0L / P.h, lo ? -P.w : 0.0L);
-  P.ka[n - 1] = xc(1.0L / P.h, hi ? -P.w : 0.0L);
+  P.ka[0] = xc(1.0L / P.h, 0.0L) + P.glo;
+  P.ka[n - 1] = xc(1.0L / P.h, 0.0L) + P.ghi;
   P.ma[0] = P.ma[n - 1] = 2.0L * P.h / 6.0L;
   P.kb = -1.0L / P.h;
   P.mb = P.h / 6.0L;
@@ -149,7 +150,7 @@ XPencil make_xpencil(int n, double h, double omega, int lo, int hi) {
 }
 
 // x^T K x without cancellation: K = (1/h) sum over elements of (e_i - e_{i+1})
-// (e_i - e_{i+1})^T minus i*w on the absorbing corners.
+// (e_i - e_{i+1})^T plus the corner terms g at the two ends.
 xc stiff_form(const XPencil& P, const std::vector<xc>& x) {
   xc s = 0.0L;
   for (int i = 0; i + 1 < P.n; ++i) {
@@ -157,8 +158,8 @@ xc stiff_form(const XPencil& P, const std::vector<xc>& x) {
     s += d * d;
   }
   s /= P.h;
-  if (P.lo) s -= xc(0.0L, P.w) * x[0] * x[0];
-  if (P.hi) s -= xc(0.0L, P.w) * x[P.n - 1] * x[P.n - 1];
+  s += P.glo * x[0] * x[0];
+  s += P.ghi * x[P.n - 1] * x[P.n - 1];
   return s;
 }
 
@@ -235,10 +236,12 @@ Refined refine(const XPencil& P, cd lam0, int steps, bool whole) {
 
 }  // namespace
 
-int eig1d(int n, double h, double omega, int lo, int hi, std::vector<cd>& lam_out,
-          std::vector<cd>& v0, std::vector<cd>& v1, std::vector<cd>* vfull, std::vector<cd>* lam_lo) {
-  if (n < 3 || !(h > 0.0) || !std::isfinite(omega)) return HELM_EINVAL;
-  const Pencil P = make_pencil(n, h, omega, lo, hi);
+int eig1d(int n, double h, cd glo, cd ghi, std::vector<cd>& lam_out, std::vector<cd>& v0,
+          std::vector<cd>& v1, std::vector<cd>* vfull, std::vector<cd>* lam_lo) {
+  if (n < 3 || !(h > 0.0) || !std::isfinite(glo.real()) || !std::isfinite(glo.imag()) ||
+      !std::isfinite(ghi.real()) || !std::isfinite(ghi.imag()))
+    return HELM_EINVAL;
+  const Pencil P = make_pencil(n, h, glo, ghi);
   // Closed-form Neumann spectrum: exact when no face absorbs, the starting
   // values of the root finder otherwise.
   std::vector<cd> lam(n);
@@ -246,10 +249,12 @@ int eig1d(int n, double h, double omega, int lo, int hi, std::vector<cd>& lam_ou
     const double t = M_PI * k / (n - 1);
     lam[k] = 6.0 * (1.0 - std::cos(t)) / (h * h * (2.0 + std::cos(t)));
   }
-  const bool absorbing = (lo || hi) && omega != 0.0;
-  if (absorbing) {
-    const double shift = 0.25 * std::abs(omega) * (lo + hi);
-    for (int k = 0; k < n; ++k) lam[k] -= cd(0.0, shift);
+  const bool robin = glo != 0.0 || ghi != 0.0;
+  if (robin) {
+    // the corner terms move the Neumann eigenvalues by about a quarter of
+    // their sum (first-order perturbation averaged over the modes)
+    const cd shift = 0.25 * (glo + ghi);
+    for (int k = 0; k < n; ++k) lam[k] += shift;
     std::vector<cd> next(n);
     std::vector<char> done(n, 0);
     const int max_sweeps = 400;
@@ -285,7 +290,7 @@ int eig1d(int n, double h, double omega, int lo, int hi, std::vector<cd>& lam_ou
       if (!std::isfinite(lam[j].real()) || !std::isfinite(lam[j].imag())) return HELM_ENOCONV;
   }
   // Refinement: 3 inverse-iteration steps with Rayleigh-quotient shifts.
-  const XPencil XP = make_xpencil(n, h, omega, lo, hi);
+  const XPencil XP = make_xpencil(n, h, glo, ghi);
   std::vector<Refined> R(n);
   double worst = 0.0;
 #pragma omp parallel for schedule(dynamic, 16) reduction(max : worst)
@@ -332,7 +337,9 @@ extern "C" int helm_eig1d(int64_t n, double h, double omega, int abc_lo, int abc
   std::vector<helm::cd> L, V0, V1;
   int st;
   try {
-    st = helm::eig1d((int)n, h, omega, abc_lo, abc_hi, L, V0, V1, nullptr, nullptr);
+    if (!std::isfinite(omega)) return HELM_EINVAL;
+    st = helm::eig1d((int)n, h, helm::face_gamma(omega, abc_lo), helm::face_gamma(omega, abc_hi), L, V0, V1,
+                     nullptr, nullptr);
   } catch (...) {
     return HELM_ENOMEM;
   }

@@ -308,4 +308,16 @@ struct ResidArgs {
 hipError_t launch_residual(const ResidArgs& a, hipStream_t s);
 int64_t residual_scratch_len(int dim, const int64_t* grid, int nb);
 
+
+// Device eigen-setup (eigdev.hip): the eigenpairs of eig1d, computed on the
+// current device on stream s; the whole eigenvectors, if `vecs` is given, go
+// to the non-null device arrays there (V[i][l] = v_l(i), its transpose, and
+// float copies of both, n x n each).
+struct EigVecOut {
+  double2 *Vd, *VTd;
+  float2 *Vf, *VTf;
+};
+int eig1d_device(int n, double h, cd glo, cd ghi, std::vector<cd>& lam, std::vector<cd>& v0,
+                 std::vector<cd>& v1, std::vector<cd>& lamlo, const EigVecOut* vecs, hipStream_t s);
+
 }  // namespace helm

@@ -31,6 +31,10 @@ namespace {
 
 bool is_pow2(int64_t n) { return n >= 2 && (n & (n - 1)) == 0; }
 
+// h times the corner entry 1/h + g of a 1D stiffness matrix (face condition
+// du/dn + g u = 0).
+double2 corner_h(double2 g, double h) { return make_double2(1.0 + h * g.x, h * g.y); }
+
 struct DevMem {
   void* p = nullptr;
   size_t bytes = 0;
@@ -70,7 +74,7 @@ struct Roots {  // e^{sign 2 pi i t / L}, t < L, in double and float
 struct PAxis {
   int n = 0;
   double h = 0;
-  int lo = 0, hi = 0;
+  double2 glo{0, 0}, ghi{0, 0};  // face coefficients g of du/dn + g u = 0
   std::vector<cd> lamA, va0, va1;
   // spectra to extended precision (host), for the shifted values below
   std::vector<long double> lamBx;
@@ -106,8 +110,11 @@ struct helm_plan {
   int dim = 0;
   int64_t grid[3] = {0, 0, 0};
   double h[3] = {0, 0, 0};
-  double omega = 0;
-  uint32_t abc = 0;
+  // operator -Lap u - c u with face conditions du/dn + g u = 0: c (and c to
+  // extended precision, for the shifts), g per axis and face
+  double cz = 0;
+  long double czx = 0;
+  double2 glo[3] = {}, ghi[3] = {};
   helm_options opt{};
   int device = 0;
   helm::PAxis ax[2];
@@ -998,7 +1005,7 @@ int solve_dense(helm_plan* p, const void* x, int x_kind, double2* u, int accumul
   LineArgs la;
   la.nb = nb;
   la.nL = p->nL;
-  la.sC = make_double2(-p->omega * p->omega, 0.0);
+  la.sC = make_double2(-p->cz, 0.0);
   la.hL = p->hL;
   la.kLo = p->kLo;
   la.kHi = p->kHi;
@@ -1045,7 +1052,7 @@ int solve_once(helm_plan* p, const void* x, int x_kind, double2* u, int accumula
                hipStream_t st) {
   if (p->dense) return solve_dense(p, x, x_kind, u, accumulate, nb, fp32, st);
   const int T = fp32 ? ST_C64 : ST_C128;
-  const double w2 = p->omega * p->omega;
+  const double w2 = p->cz;
   void* W0 = p->W0.p;
   void* W1 = p->W1.p;
   if (p->dim == 2) {
@@ -1121,8 +1128,8 @@ int solve_once(helm_plan* p, const void* x, int x_kind, double2* u, int accumula
     om.w2 = w2;
     om.h2 = A2.h;
     om.h3 = p->hL;
-    om.k2Lo = make_double2(1.0, A2.lo ? -p->omega * A2.h : 0.0);
-    om.k2Hi = make_double2(1.0, A2.hi ? -p->omega * A2.h : 0.0);
+    om.k2Lo = corner_h(A2.glo, A2.h);
+    om.k2Hi = corner_h(A2.ghi, A2.h);
     om.k3Lo = p->kLo;
     om.k3Hi = p->kHi;
     HCHK(timed(p, K_OUTER_MID, (double)nb * 2 * plane * sizeof(double2) * 3, st, [&] { return launch_outer_mid(om, st); }));
@@ -1288,11 +1295,10 @@ ResidArgs resid_args(helm_plan* p, int nb) {
   for (int j = 0; j < p->dim; ++j) {
     a.ax[j].n = (int)p->grid[j];
     a.ax[j].h = p->h[j];
-    const int lo = (p->abc >> (2 * j)) & 1, hi = (p->abc >> (2 * j + 1)) & 1;
-    a.ax[j].kLo = make_double2(1.0, lo ? -p->omega * p->h[j] : 0.0);
-    a.ax[j].kHi = make_double2(1.0, hi ? -p->omega * p->h[j] : 0.0);
+    a.ax[j].kLo = corner_h(p->glo[j], p->h[j]);
+    a.ax[j].kHi = corner_h(p->ghi[j], p->h[j]);
   }
-  a.w2 = p->omega * p->omega;
+  a.w2 = p->cz;
   a.norms = p->norms.as<double>();
   a.scratch = p->scratch.as<double>();
   a.scratch_len = (int64_t)(p->scratch.bytes / sizeof(double));
@@ -1331,6 +1337,22 @@ int residual_norms(helm_plan* p, const double2* u, const double2* f, void* r, in
 }
 
 // Upload V[i][l] = v_l(i) and V^T, interleaved complex, in double and float.
+// The four eigenvector arrays of an axis (V, V^T in double, then in float),
+// for the device eigen-setup to fill.
+int eigvec_buffers(PAxis& a, EigVecOut* o) {
+  const size_t nn = (size_t)a.n * a.n;
+  const size_t bd = 2 * nn * sizeof(double2), bf = 2 * nn * sizeof(float2);
+  if (a.vmat.ensure(bd + bf) != hipSuccess) return HELM_ENOMEM;
+  double2* d = a.vmat.as<double2>();
+  float2* f = reinterpret_cast<float2*>((char*)a.vmat.p + bd);
+  a.Vd = d;
+  a.VTd = d + nn;
+  a.Vf = f;
+  a.VTf = f + nn;
+  *o = EigVecOut{d, d + nn, f, f + nn};
+  return HELM_OK;
+}
+
 int upload_eigvecs(PAxis& a, const std::vector<cd>& v) {
   const size_t n = (size_t)a.n, nn = n * n;
   std::vector<double2> hd(2 * nn);
@@ -1355,7 +1377,7 @@ int upload_eigvecs(PAxis& a, const std::vector<cd>& v) {
   return HELM_OK;
 }
 
-void fill_axis_tables_host(PAxis& a, double omega, std::vector<double2>& buf, std::vector<double>& invmu) {
+void fill_axis_tables_host(PAxis& a, long double czx, std::vector<double2>& buf, std::vector<double>& invmu) {
   const int n = a.n;
   const double h = a.h;
   buf.assign((size_t)n * 8, make_double2(0, 0));
@@ -1367,7 +1389,7 @@ void fill_axis_tables_host(PAxis& a, double omega, std::vector<double2>& buf, st
     const double omc = 2.0 * sh * sh;  // 1 - cos(theta) without cancellation
     const double cth = 1.0 - omc;
     const double mu = h / 6.0 * (4.0 + 2.0 * cth);
-    const long double w2x = (long double)omega * (long double)omega;
+    const long double w2x = czx;
     const long double thx = 2.0L * (long double)M_PI * l / n;
     const long double shx = std::sin(0.5L * thx);
     const long double omcx = 2.0L * shx * shx;
@@ -1385,13 +1407,13 @@ void fill_axis_tables_host(PAxis& a, double omega, std::vector<double2>& buf, st
     buf[7 * n + l] = hd2(a.va1[l]);
     invmu[l] = 1.0 / mu;
   }
-  // B - A on the two end nodes of this axis
-  a.bd.dK[0][0] = make_double2(1.0 / h, a.lo ? omega : 0.0);
-  a.bd.dK[1][1] = make_double2(1.0 / h, a.hi ? omega : 0.0);
+  // B - A on the two end nodes of this axis: the periodic corner 2/h against
+  // the face's 1/h + g
+  a.bd.dK[0][0] = make_double2(1.0 / h - a.glo.x, -a.glo.y);
+  a.bd.dK[1][1] = make_double2(1.0 / h - a.ghi.x, -a.ghi.y);
   a.bd.dK[0][1] = a.bd.dK[1][0] = make_double2(-1.0 / h, 0.0);
   a.bd.dM[0][0] = a.bd.dM[1][1] = 2.0 * h / 6.0;
   a.bd.dM[0][1] = a.bd.dM[1][0] = h / 6.0;
-  (void)omega;
 }
 
 
@@ -2217,6 +2239,7 @@ void helm_default_options(helm_options* opt) {
   opt->transform = HELM_TRANSFORM_FFT;
   opt->tune_cache = nullptr;
   opt->boundary = HELM_BOUNDARY_AUTO;
+  opt->eigen = HELM_EIGEN_AUTO;
 }
 
 const char* helm_strerror(int code) {
@@ -2233,22 +2256,99 @@ const char* helm_strerror(int code) {
   }
 }
 
+}  // extern "C"
+
+namespace {
+
+// Which coefficient sets the method handles (every line system and the
+// operator nonsingular):
+//  * c = 0 and g = 0 on every face: A annihilates the constants (ESINGULAR);
+//  * some face of the last axis with Im g != 0, and no two faces with Im g
+//    of opposite signs: with sigma real (periodic branch) the imaginary part
+//    of v^H T v is sum Im g |v_face|^2, nonzero for a null vector of an
+//    irreducible tridiagonal T, and the absorbing-branch sigma carry
+//    imaginary parts of the same sign;
+//  * all g real and >= 0, and c < 0, or c = 0 with g > 0 on a face of the
+//    last axis: every line matrix sigma M + K is symmetric positive definite;
+//  * otherwise (c > 0 with real faces on the last axis, mixed signs)
+//    resonant line systems are possible: EUNSUPPORTED.
+int check_coefficients(int dim, double c, const double2* glo, const double2* ghi) {
+  if (!std::isfinite(c)) return HELM_EINVAL;
+  bool all_zero = c == 0.0, all_real = true, neg_re = false, pos_im = false, neg_im = false;
+  for (int j = 0; j < dim; ++j) {
+    for (const double2 g : {glo[j], ghi[j]}) {
+      if (!std::isfinite(g.x) || !std::isfinite(g.y)) return HELM_EINVAL;
+      all_zero = all_zero && g.x == 0.0 && g.y == 0.0;
+      all_real = all_real && g.y == 0.0;
+      neg_re = neg_re || g.x < 0.0;
+      pos_im = pos_im || g.y > 0.0;
+      neg_im = neg_im || g.y < 0.0;
+    }
+  }
+  if (all_zero) return HELM_ESINGULAR;
+  const int last = dim - 1;
+  if (glo[last].y != 0.0 || ghi[last].y != 0.0) return (pos_im && neg_im) ? HELM_EUNSUPPORTED : HELM_OK;
+  if (!all_real || neg_re) return HELM_EUNSUPPORTED;
+  if (c < 0.0) return HELM_OK;
+  if (c == 0.0 && (glo[last].x > 0.0 || ghi[last].x > 0.0)) return HELM_OK;
+  return HELM_EUNSUPPORTED;
+}
+
+int setup_impl(int dim, const int64_t* grid, const double* h, double c, long double cx, const double2* glo,
+               const double2* ghi, const helm_options* opt, helm_plan** out);
+
+}  // namespace
+
+extern "C" {
+
 int helm_setup(int dim, const int64_t* grid, const double* h, double omega, uint32_t abc,
                const helm_options* opt, helm_plan** out) {
   if (!out || !grid || !h || (dim != 2 && dim != 3)) return HELM_EINVAL;
   *out = nullptr;
-  for (int j = 0; j < dim; ++j)
-    if (grid[j] < 3 || grid[j] > (1 << 24) || !(h[j] > 0.0) || !std::isfinite(h[j])) return HELM_EINVAL;
   if (!std::isfinite(omega)) return HELM_EINVAL;
   if (abc >> (2 * dim)) return HELM_EINVAL;
-  if (omega == 0.0) return HELM_ESINGULAR;  // absorbing faces degenerate to Neumann: constants in the kernel
+  double2 glo[3], ghi[3];
+  for (int j = 0; j < dim; ++j) {
+    const cd gl = face_gamma(omega, (abc >> (2 * j)) & 1), gh = face_gamma(omega, (abc >> (2 * j + 1)) & 1);
+    glo[j] = make_double2(gl.real(), gl.imag());
+    ghi[j] = make_double2(gh.real(), gh.imag());
+  }
+  // c = omega^2; the shifts take it to extended precision
+  return setup_impl(dim, grid, h, omega * omega, (long double)omega * (long double)omega, glo, ghi, opt, out);
+}
+
+int helm_setup_general(int dim, const int64_t* grid, const double* h, double c, const double* gamma,
+                       const helm_options* opt, helm_plan** out) {
+  if (!out || !grid || !h || !gamma || (dim != 2 && dim != 3)) return HELM_EINVAL;
+  *out = nullptr;
+  double2 glo[3], ghi[3];
+  for (int j = 0; j < dim; ++j) {
+    glo[j] = make_double2(gamma[4 * j], gamma[4 * j + 1]);
+    ghi[j] = make_double2(gamma[4 * j + 2], gamma[4 * j + 3]);
+  }
+  return setup_impl(dim, grid, h, c, (long double)c, glo, ghi, opt, out);
+}
+
+}  // extern "C"
+
+namespace {
+
+int setup_impl(int dim, const int64_t* grid, const double* h, double c, long double cx, const double2* glo,
+               const double2* ghi, const helm_options* opt, helm_plan** out) {
+  for (int j = 0; j < dim; ++j)
+    if (grid[j] < 3 || grid[j] > (1 << 24) || !(h[j] > 0.0) || !std::isfinite(h[j])) return HELM_EINVAL;
+  const int chk = check_coefficients(dim, c, glo, ghi);
+  if (chk != HELM_OK) return chk;
   const int last = dim - 1;
-  if (!((abc >> (2 * last)) & 3)) return HELM_EUNSUPPORTED;  // last axis needs an absorbing face
   std::unique_ptr<helm_plan> p(new (std::nothrow) helm_plan());
   if (!p) return HELM_ENOMEM;
   p->dim = dim;
-  p->omega = omega;
-  p->abc = abc;
+  p->cz = c;
+  p->czx = cx;
+  for (int j = 0; j < dim; ++j) {
+    p->glo[j] = glo[j];
+    p->ghi[j] = ghi[j];
+  }
   helm_default_options(&p->opt);
   if (opt) p->opt = *opt;
   if (p->opt.precision != HELM_PREC_FP64 && p->opt.precision != HELM_PREC_MIXED) return HELM_EINVAL;
@@ -2258,6 +2358,8 @@ int helm_setup(int dim, const int64_t* grid, const double* h, double omega, uint
   const int bmode = p->opt.boundary;
   if (bmode != HELM_BOUNDARY_AUTO && bmode != HELM_BOUNDARY_LINES && bmode != HELM_BOUNDARY_TABLES)
     return HELM_EINVAL;
+  const int emode = p->opt.eigen;
+  if (emode != HELM_EIGEN_AUTO && emode != HELM_EIGEN_HOST && emode != HELM_EIGEN_DEVICE) return HELM_EINVAL;
   const bool want_tab = dim == 3 && bmode != HELM_BOUNDARY_LINES && tf != HELM_TRANSFORM_DENSE;
   if (p->opt.tune_cache) p->tune_path = p->opt.tune_cache;
   p->opt.tune_cache = nullptr;
@@ -2282,15 +2384,15 @@ int helm_setup(int dim, const int64_t* grid, const double* h, double omega, uint
   p->nper = dim - 1;
   p->nL = (int)grid[last];
   p->hL = h[last];
-  p->kLo = make_double2(1.0, ((abc >> (2 * last)) & 1) ? -omega * h[last] : 0.0);
-  p->kHi = make_double2(1.0, ((abc >> (2 * last + 1)) & 1) ? -omega * h[last] : 0.0);
+  p->kLo = corner_h(glo[last], h[last]);
+  p->kHi = corner_h(ghi[last], h[last]);
   if (p->nL > 4097) return HELM_EUNSUPPORTED;
   for (int j = 0; j < p->nper; ++j) {
     PAxis& a = p->ax[j];
     a.n = (int)grid[j];
     a.h = h[j];
-    a.lo = (abc >> (2 * j)) & 1;
-    a.hi = (abc >> (2 * j + 1)) & 1;
+    a.glo = glo[j];
+    a.ghi = ghi[j];
     if (is_pow2(a.n)) {
       pow2_split(a.n, &a.na, &a.nbp);
       if (a.na > 512 || a.nbp > 512) return HELM_EUNSUPPORTED;
@@ -2302,19 +2404,31 @@ int helm_setup(int dim, const int64_t* grid, const double* h, double omega, uint
     // whole eigenvectors: both axes for the dense transform, the inner one
     // for the boundary tables
     const bool vecs = dense_ok || (want_tab && j == 1);
-    const int st = eig1d(a.n, a.h, omega, a.lo, a.hi, a.lamA, a.va0, a.va1, vecs ? &vfull : nullptr, &lamlo);
-    if (st != HELM_OK) return st;
+    if (emode == HELM_EIGEN_HOST) {
+      const int st = eig1d(a.n, a.h, cd(a.glo.x, a.glo.y), cd(a.ghi.x, a.ghi.y), a.lamA, a.va0, a.va1,
+                           vecs ? &vfull : nullptr, &lamlo);
+      if (st != HELM_OK) return st;
+      if (vecs) {
+        const int ast = upload_eigvecs(a, vfull);
+        if (ast != HELM_OK) return ast;
+      }
+    } else {
+      EigVecOut vo{};
+      if (vecs) {
+        const int ast = eigvec_buffers(a, &vo);
+        if (ast != HELM_OK) return ast;
+      }
+      const int st = eig1d_device(a.n, a.h, cd(a.glo.x, a.glo.y), cd(a.ghi.x, a.ghi.y), a.lamA, a.va0, a.va1, lamlo,
+                                  vecs ? &vo : nullptr, nullptr);
+      if (st != HELM_OK) return st;
+    }
     a.lamAx.resize(a.n);
     for (int l = 0; l < a.n; ++l)
       a.lamAx[l] = std::complex<long double>((long double)a.lamA[l].real() + lamlo[l].real(),
                                              (long double)a.lamA[l].imag() + lamlo[l].imag());
-    if (vecs) {
-      const int ast = upload_eigvecs(a, vfull);
-      if (ast != HELM_OK) return ast;
-    }
     std::vector<double2> buf;
     std::vector<double> invmu;
-    fill_axis_tables_host(a, omega, buf, invmu);
+    fill_axis_tables_host(a, cx, buf, invmu);
     const size_t nb2 = (size_t)a.n * 8 * sizeof(double2);
     if (a.tab.ensure(nb2 + (size_t)a.n * sizeof(double)) != hipSuccess) return HELM_ENOMEM;
     if (upload(a.tab.p, buf.data(), nb2) != hipSuccess) return HELM_EDEVICE;
@@ -2344,7 +2458,7 @@ int helm_setup(int dim, const int64_t* grid, const double* h, double omega, uint
     const PAxis& inner = p->ax[dim - 2];
     const size_t pairs = (size_t)nO * nI;
     std::vector<double2> hs(pairs * fam);
-    const long double w2x = (long double)omega * (long double)omega;
+    const long double w2x = p->czx;
     for (int k = 0; k < fam; ++k) {
       for (int l = 0; l < nO; ++l) {
         std::complex<long double> so(0.0L, 0.0L);
@@ -2410,6 +2524,10 @@ int helm_setup(int dim, const int64_t* grid, const double* h, double omega, uint
   *out = p.release();
   return HELM_OK;
 }
+
+}  // namespace
+
+extern "C" {
 
 int helm_solve(helm_plan* p, const void* f, void* u, int nrhs, void* stream) {
   return helm::solve_entry(p, f, u, nrhs, reinterpret_cast<hipStream_t>(stream), true);

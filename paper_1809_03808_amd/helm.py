@@ -32,11 +32,15 @@ DENSE_MAX = 1024
 BOUNDARY_AUTO = 0
 BOUNDARY_LINES = 1
 BOUNDARY_TABLES = 2
+EIGEN_AUTO = 0
+EIGEN_HOST = 1
+EIGEN_DEVICE = 2
 
 # Every symbol declared in include/helm.h.
 EXPORTS = (
     "helm_default_options", "helm_setup", "helm_solve", "helm_report_get",
-    "helm_residual", "helm_destroy", "helm_strerror", "helm_eig1d",
+    "helm_residual", "helm_destroy", "helm_strerror", "helm_eig1d", "helm_eig1d_device",
+    "helm_setup_general",
     "helm_profile", "helm_kernel_stats_get", "helm_kernel_name",
     "helm_batch_create", "helm_batch_solve", "helm_batch_report_get", "helm_batch_destroy",
     "helm_solve_static",
@@ -52,7 +56,7 @@ class Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("tol", ctypes.c_double),
                 ("max_iter", ctypes.c_int), ("check", ctypes.c_int),
                 ("transform", ctypes.c_int), ("tune_cache", ctypes.c_char_p),
-                ("boundary", ctypes.c_int)]
+                ("boundary", ctypes.c_int), ("eigen", ctypes.c_int)]
 
 
 class Report(ctypes.Structure):
@@ -84,6 +88,14 @@ def lib():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise OSError(f"{LIB_PATH} not found: build it with `python -m paper_1809_03808_amd.build`")
+    # The library shares the process's HIP runtime with PyTorch (device
+    # tensors are passed to it): PyTorch loaded first, the library binds to
+    # the runtime PyTorch brought in instead of loading a second copy, which
+    # would leave PyTorch without a device.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = ctypes.CDLL(LIB_PATH)
     vp, i64p, dp = ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)
     L.helm_default_options.argtypes = [ctypes.POINTER(Options)]
@@ -91,6 +103,9 @@ def lib():
     L.helm_setup.argtypes = [ctypes.c_int, i64p, dp, ctypes.c_double, ctypes.c_uint32,
                              ctypes.POINTER(Options), ctypes.POINTER(vp)]
     L.helm_setup.restype = ctypes.c_int
+    L.helm_setup_general.argtypes = [ctypes.c_int, i64p, dp, ctypes.c_double, dp,
+                                     ctypes.POINTER(Options), ctypes.POINTER(vp)]
+    L.helm_setup_general.restype = ctypes.c_int
     L.helm_solve.argtypes = [vp, vp, vp, ctypes.c_int, vp]
     L.helm_solve.restype = ctypes.c_int
     L.helm_solve_static.argtypes = [vp, vp, vp, ctypes.c_int, vp]
@@ -106,6 +121,8 @@ def lib():
     L.helm_eig1d.argtypes = [ctypes.c_int64, ctypes.c_double, ctypes.c_double, ctypes.c_int,
                              ctypes.c_int, dp, dp]
     L.helm_eig1d.restype = ctypes.c_int
+    L.helm_eig1d_device.argtypes = L.helm_eig1d.argtypes
+    L.helm_eig1d_device.restype = ctypes.c_int
     L.helm_profile.argtypes = [vp, ctypes.c_int]
     L.helm_profile.restype = ctypes.c_int
     L.helm_kernel_stats_get.argtypes = [vp, ctypes.POINTER(KernelStats), ctypes.c_int]
@@ -137,15 +154,18 @@ def abc_mask(abc):
     return m
 
 
-def eig1d(n, h, omega, abc_lo=True, abc_hi=True):
-    """Host FP64 eigen-setup: (lambda[n] complex, vb[2][n] complex)."""
+def eig1d(n, h, omega, abc_lo=True, abc_hi=True, device=False):
+    """Absorbing-boundary eigen-setup (helm_eig1d on the host, or
+    helm_eig1d_device on the current HIP device): (lambda[n] complex,
+    vb[2][n] complex)."""
     lam = np.zeros(2 * n)
     vb = np.zeros(4 * n)
-    rc = lib().helm_eig1d(int(n), float(h), float(omega), int(bool(abc_lo)), int(bool(abc_hi)),
-                          lam.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
-                          vb.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    fn = lib().helm_eig1d_device if device else lib().helm_eig1d
+    rc = fn(int(n), float(h), float(omega), int(bool(abc_lo)), int(bool(abc_hi)),
+            lam.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+            vb.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
     if rc != HELM_OK:
-        raise HelmError(rc, "helm_eig1d")
+        raise HelmError(rc, "helm_eig1d_device" if device else "helm_eig1d")
     lam = lam.view(np.complex128)
     vb = vb.view(np.complex128).reshape(2, n)
     return lam, vb
@@ -169,11 +189,29 @@ def _check_tensor(t, grid, name):
     return 1 if t.dim() == len(grid) else int(np.prod(t.shape[:-len(grid)]))
 
 
+def face_coefficients(omega, faces):
+    """gamma array of helm_setup_general from per-axis (lo, hi) faces: a
+    boolean face is absorbing (g = -i omega) or Neumann (g = 0), a number is
+    the Robin coefficient g itself."""
+    out = []
+    for pair in faces:
+        for face in pair:
+            if isinstance(face, (bool, np.bool_)):
+                g = complex(0.0, -omega) if face else 0j
+            else:
+                g = complex(face)
+            out += [g.real, g.imag]
+    return out
+
+
 class Plan:
-    """A solver plan: ``Plan(grid, h, omega, abc)`` then ``plan.solve(f, u)``."""
+    """A solver plan: ``Plan(grid, h, omega, abc)`` then ``plan.solve(f, u)``.
+    With ``c`` given, or ``abc`` holding numeric faces, the plan is built by
+    helm_setup_general for -Lap u - c u = f with du/dn + g u = 0 on each face
+    (c defaults to omega^2, boolean faces as in helm_setup)."""
 
     def __init__(self, grid, h, omega, abc=None, precision=PREC_FP64, tol=1e-10, max_iter=8,
-                 check=True, transform=None, tune_cache=None, boundary=None):
+                 check=True, transform=None, tune_cache=None, boundary=None, eigen=None, c=None):
         L = lib()
         self.grid = tuple(int(n) for n in grid)
         self.dim = len(self.grid)
@@ -181,7 +219,18 @@ class Plan:
         self.omega = float(omega)
         if abc is None:
             abc = (1 << (2 * self.dim)) - 1
-        self.abc = abc if isinstance(abc, int) else abc_mask(abc)
+        general = c is not None or (not isinstance(abc, int) and any(
+            not isinstance(f, (bool, np.bool_)) for pair in abc for f in pair))
+        if general:
+            faces = abc if not isinstance(abc, int) else [
+                (bool((abc >> (2 * j)) & 1), bool((abc >> (2 * j + 1)) & 1)) for j in range(self.dim)]
+            self.faces = tuple(tuple(p) for p in faces)
+            self.c = float(self.omega ** 2 if c is None else c)
+            self.abc = None
+        else:
+            self.abc = abc if isinstance(abc, int) else abc_mask(abc)
+            self.faces = None
+            self.c = self.omega ** 2
         opt = Options()
         L.helm_default_options(ctypes.byref(opt))
         opt.precision = int(precision)
@@ -192,13 +241,19 @@ class Plan:
             opt.transform = int(transform)
         if boundary is not None:
             opt.boundary = int(boundary)
+        if eigen is not None:
+            opt.eigen = int(eigen)
         self._tune = tune_cache.encode() if tune_cache else None
         opt.tune_cache = self._tune
         g = (ctypes.c_int64 * self.dim)(*self.grid)
         hh = (ctypes.c_double * self.dim)(*self.h)
         out = ctypes.c_void_p()
-        rc = L.helm_setup(self.dim, g, hh, self.omega, ctypes.c_uint32(self.abc), ctypes.byref(opt),
-                          ctypes.byref(out))
+        if general:
+            gam = (ctypes.c_double * (4 * self.dim))(*face_coefficients(self.omega, self.faces))
+            rc = L.helm_setup_general(self.dim, g, hh, self.c, gam, ctypes.byref(opt), ctypes.byref(out))
+        else:
+            rc = L.helm_setup(self.dim, g, hh, self.omega, ctypes.c_uint32(self.abc), ctypes.byref(opt),
+                              ctypes.byref(out))
         if rc != HELM_OK:
             raise HelmError(rc, "helm_setup")
         self._p = out

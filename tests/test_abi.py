@@ -39,6 +39,7 @@ def test_strerror_and_defaults():
     helm.lib().helm_default_options(ctypes.byref(opt))
     assert opt.precision == helm.PREC_FP64 and opt.tol == 1e-10 and opt.max_iter == 8 and opt.check == 1
     assert opt.transform == helm.TRANSFORM_FFT and opt.boundary == helm.BOUNDARY_AUTO
+    assert opt.eigen == helm.EIGEN_AUTO
 
 
 def test_setup_rejects_unknown_boundary_mode():
@@ -47,10 +48,19 @@ def test_setup_rejects_unknown_boundary_mode():
     assert e.value.code == helm.HELM_EINVAL
 
 
-def test_eig1d_rejects_bad_arguments():
+def test_setup_rejects_unknown_eigen_mode():
     with pytest.raises(helm.HelmError) as e:
-        helm.eig1d(2, 0.5, 1.0)
+        helm.Plan((8, 8), (0.1,) * 2, 3.0, eigen=5)
     assert e.value.code == helm.HELM_EINVAL
+
+
+@pytest.mark.parametrize("device", [False, True])
+def test_eig1d_rejects_bad_arguments(device):
+    # argument errors are returned before any device call
+    for args in ((2, 0.5, 1.0), (8, 0.0, 1.0), (8, 0.1, float("nan"))):
+        with pytest.raises(helm.HelmError) as e:
+            helm.eig1d(*args, device=device)
+        assert e.value.code == helm.HELM_EINVAL
 
 
 @pytest.mark.parametrize("grid,h,omega,mask,code", [
@@ -100,3 +110,24 @@ def test_setup_size_limits(grid):
     with pytest.raises(helm.HelmError) as e:
         helm.Plan(grid, h, 5.0)
     assert e.value.code == helm.HELM_EUNSUPPORTED
+
+
+@pytest.mark.parametrize("c,faces,code", [
+    (0.0, ((0.0, 0.0), (0.0, 0.0)), helm.HELM_ESINGULAR),          # Neumann Laplace: constants
+    (float("nan"), ((1.0, 1.0), (1.0, 1.0)), helm.HELM_EINVAL),
+    (-1.0, ((1.0, float("inf")), (1.0, 1.0)), helm.HELM_EINVAL),
+    (9.0, ((1.0, 1.0), (1.0, 1.0)), helm.HELM_EUNSUPPORTED),        # c > 0, real faces: resonance possible
+    (-4.0, ((-2j, 3j), (-1j, -1j)), helm.HELM_EUNSUPPORTED),        # imaginary parts of both signs
+    (-4.0, ((1.0, 1.0), (-0.5, 1.0)), helm.HELM_EUNSUPPORTED),      # negative real g
+    (0.0, ((1.0, 1.0), (0.0, 0.0)), helm.HELM_EUNSUPPORTED),        # Laplace, Neumann last axis
+    (4.0, ((-2j, -2j), (0.0, 0.0)), helm.HELM_EUNSUPPORTED),        # real faces on the last axis, c > 0
+])
+def test_setup_general_rejects_coefficients(c, faces, code):
+    """helm_setup_general's coefficient checks run before any device call."""
+    with pytest.raises(helm.HelmError) as e:
+        helm.Plan((8, 8), (1 / 7, 1 / 7), 2.0, faces, c=c)
+    assert e.value.code == code
+
+
+def test_face_coefficients_follow_helm_setup():
+    assert helm.face_coefficients(3.0, ((True, False), (0.5 - 1j, True))) == [0.0, -3.0, 0.0, 0.0, 0.5, -1.0, 0.0, -3.0]
