@@ -257,6 +257,7 @@ int eig1d(int n, double h, cd glo, cd ghi, std::vector<cd>& lam_out, std::vector
     for (int k = 0; k < n; ++k) lam[k] += shift;
     std::vector<cd> next(n);
     std::vector<char> done(n, 0);
+    std::vector<double> prev(n, INFINITY);  // |correction| of the previous sweep
     const int max_sweeps = 400;
     int sweep = 0;
     for (; sweep < max_sweeps; ++sweep) {
@@ -279,9 +280,14 @@ int eig1d(int n, double h, cd glo, cd ghi, std::vector<cd>& lam_out, std::vector
         const cd corr = N / (1.0 - N * sum);
         next[j] = lam[j] - corr;
         // FP64 rounding floor of the determinant recurrence is ~1e-13 relative;
-        // the inverse iteration below supplies the last digits.
-        if (std::abs(corr) <= 1e-12 * std::abs(lam[j]) + 1e-300) done[j] = 1;
+        // the inverse iteration below supplies the last digits.  A root
+        // also stops once its correction is below 1e-9 relative and no
+        // longer halves from one sweep to the next: it then sits on that
+        // floor, well inside the convergence region of the inverse iteration.
+        const double ac = std::abs(corr), al = std::abs(lam[j]);
+        if (ac <= 1e-12 * al + 1e-300 || (ac <= 1e-9 * al && ac >= 0.5 * prev[j])) done[j] = 1;
         else ++active;
+        prev[j] = ac;
       }
       lam.swap(next);
       if (active == 0) break;

@@ -152,6 +152,7 @@ struct AberthArgs {
   PencilArgs P;
   double2* buf[2];  // roots, ping-pong: sweep s reads buf[s & 1], writes buf[(s + 1) & 1]
   int* done;        // [n] root converged
+  double* prev;     // [n] |correction| of the previous sweep
   int* cnt;         // [max sweeps] roots still moving after sweep s
 };
 
@@ -161,8 +162,10 @@ constexpr int kAberthThreads = 256;
 // lam_j <- lam_j - N / (1 - N sum_{i != j} 1 / (lam_j - lam_i)), N = p / p'.
 // A root stops when its correction is below 1e-12 |lam_j| (the FP64 floor of
 // the determinant recurrence is about 1e-13 relative; the inverse iteration
-// supplies the last digits).  Returns at once after a sweep that left no root
-// moving.
+// supplies the last digits), or once the correction is below 1e-9 |lam_j|
+// and no longer halves from one sweep to the next (it sits on that floor;
+// without this rule a few roots at n = 2049 run all 400 sweeps).  Returns at
+// once after a sweep that left no root moving.
 __global__ __launch_bounds__(kAberthThreads) void aberth_kernel(AberthArgs a, int s) {
   if (s > 0 && a.cnt[s - 1] == 0) return;
   __shared__ double2 tile[kAberthThreads];
@@ -201,8 +204,10 @@ __global__ __launch_bounds__(kAberthThreads) void aberth_kernel(AberthArgs a, in
   const double2 N = cdiv2(make_double2(1, 0), lp);
   const double2 corr = cdiv2(N, csub(make_double2(1, 0), cmul(N, sum)));
   next[j] = csub(lj, corr);
-  if (hypot(corr.x, corr.y) <= 1e-12 * hypot(lj.x, lj.y) + 1e-300) a.done[j] = 1;
+  const double ac = hypot(corr.x, corr.y), al = hypot(lj.x, lj.y);
+  if (ac <= 1e-12 * al + 1e-300 || (ac <= 1e-9 * al && ac >= 0.5 * a.prev[j])) a.done[j] = 1;
   else atomicAdd(&a.cnt[s], 1);
+  a.prev[j] = ac;
 }
 
 struct RefineArgs {
@@ -457,7 +462,12 @@ int eig1d_device(int n, double h, cd glo, cd ghi, std::vector<cd>& lam_out, std:
   if (absorbing) {
     if (hipMemsetAsync(done, 0, nsz * sizeof(int), s) != hipSuccess) return HELM_EDEVICE;
     if (hipMemsetAsync(cnt, 0, (size_t)max_sweeps * sizeof(int), s) != hipSuccess) return HELM_EDEVICE;
-    AberthArgs A{P, {b0, b1}, done, cnt};
+    // the backward-error array is free until the refinement: it holds the
+    // previous corrections, +inf at the start
+    std::vector<double> inf(nsz, INFINITY);
+    if (hipMemcpyAsync(rres, inf.data(), nsz * sizeof(double), hipMemcpyHostToDevice, s) != hipSuccess)
+      return HELM_EDEVICE;
+    AberthArgs A{P, {b0, b1}, done, rres, cnt};
     const unsigned blocks = (unsigned)((n + kAberthThreads - 1) / kAberthThreads);
     int last = -1;
     std::vector<int> hc(chunk_sweeps);
