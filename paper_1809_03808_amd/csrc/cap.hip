@@ -14,10 +14,9 @@
 // eigenvector transform, sum over the outer modes l).
 //
 // Kernel: blocks of 256 threads per (group, output rows (k, x)); each lane
-// accumulates a 4-row x 4-right-hand-side tile in registers while streaming
+// accumulates a tile of rows x right-hand sides in registers while streaming
 // its rows of the table, which is read from memory once per launch for up to
-// 16 right-hand sides (the waves of a block that share rows take different
-// right-hand sides).  The table is symmetric (T_j^{-1} is complex
+// 16 right-hand sides.  The table is symmetric (T_j^{-1} is complex
 // symmetric), so row r of the product reads column r of the stored blocks:
 // consecutive lanes read consecutive addresses.  The input vectors are the
 // same for every lane of a wave, so their loads are uniform (scalar) loads.
@@ -29,18 +28,17 @@ namespace {
 
 constexpr int kCapThreads = 256;
 
-// Register tile: each lane computes 4 rows (r0 + lane + 64 i) times TN
+// Register tile: each lane computes TM rows (r0 + lane + 64 i) times TN
 // right-hand sides; RG waves of a block share its rows and take consecutive
-// groups of TN right-hand sides, so a block covers 256 * 4 / RG rows and
+// groups of TN right-hand sides, so a block covers 256 * TM / RG rows and
 // RG * TN right-hand sides per pass over the table.  Table entries of type
 // TT (complex128, or complex64 for the mixed-precision path) are widened to
 // FP64 and accumulated in FP64.
-template <typename TT, int TN, int RG>
+template <typename TT, int TM, int TN, int RG>
 __global__ __launch_bounds__(kCapThreads) void cap_apply_kernel(const TT* __restrict__ T0,
                                                                 const TT* __restrict__ T1,
                                                                 const double2* __restrict__ in,
                                                                 double2* __restrict__ out, CapArgs a) {
-  constexpr int TM = 4;
   constexpr int RPB = 64 * TM * (4 / RG);  // rows per block
   if (a.skip && *a.skip) return;
   const int nL = a.nL, rows = 2 * nL;
@@ -93,26 +91,95 @@ __global__ __launch_bounds__(kCapThreads) void cap_apply_kernel(const TT* __rest
   }
 }
 
-template <typename TT, int TN, int RG>
+// Sixteen right-hand sides per pass, one row per lane, every wave of a block
+// on its own rows: the table is fetched once per 16 right-hand sides.  The
+// boundary vectors of the block's group go through LDS in chunks of kCapXC
+// entries (every lane of a wave reads the same entry: broadcasts), which
+// keeps the 16 vectors out of the scalar registers.
+constexpr int kCapXC = 32;
+
+template <typename TT>
+__global__ __launch_bounds__(kCapThreads) void cap_apply16_kernel(const TT* __restrict__ T0,
+                                                                  const TT* __restrict__ T1,
+                                                                  const double2* __restrict__ in,
+                                                                  double2* __restrict__ out, CapArgs a) {
+  constexpr int TN = 16;
+  __shared__ double2 xs[TN][kCapXC];
+  if (a.skip && *a.skip) return;
+  const int nL = a.nL, rows = 2 * nL;
+  const int rt = (rows + kCapThreads - 1) / kCapThreads;
+  const int g = (int)(blockIdx.x / rt);
+  const int r = (int)(blockIdx.x % rt) * kCapThreads + (int)threadIdx.x;
+  const int ro = min(r, rows - 1);
+  for (int b0 = 0; b0 < a.nb; b0 += TN) {
+    double2 acc[TN];
+#pragma unroll
+    for (int j = 0; j < TN; ++j) acc[j] = make_double2(0, 0);
+    for (int kp = 0; kp < 2; ++kp) {
+      const TT* T = (kp ? T1 : T0) + (int64_t)g * nL * rows + ro;  // column ro of this group's [x'][rows] block
+      for (int x0 = 0; x0 < nL; x0 += kCapXC) {
+        __syncthreads();  // the previous chunk is consumed
+        for (int e = (int)threadIdx.x; e < TN * kCapXC; e += kCapThreads) {
+          const int j = e / kCapXC, x = x0 + (e - j * kCapXC);
+          // right-hand sides past nb repeat the last one; their products are dropped
+          const int b = b0 + j < a.nb ? b0 + j : a.nb - 1;
+          xs[j][e - j * kCapXC] =
+              x < nL ? in[(int64_t)b * a.in_b + (int64_t)g * a.in_g + (int64_t)kp * a.in_k + x] : make_double2(0, 0);
+        }
+        __syncthreads();
+        const int xn = min(kCapXC, nL - x0);
+#pragma unroll 4
+        for (int x = 0; x < xn; ++x) {
+          const double2 t = to_d2(T[(int64_t)(x0 + x) * rows]);
+#pragma unroll
+          for (int j = 0; j < TN; ++j) acc[j] = cfma(t, xs[j][x], acc[j]);
+        }
+      }
+    }
+    if (r < rows) {
+      const int k = r >= nL ? 1 : 0, x = r - k * nL;
+      double2* o = out + (int64_t)g * a.out_g + k * a.out_k + x;
+#pragma unroll
+      for (int j = 0; j < TN; ++j)
+        if (b0 + j < a.nb) o[(int64_t)(b0 + j) * a.out_b] = acc[j];
+    }
+  }
+}
+
+template <typename TT>
+hipError_t launch_16(const CapArgs& a, hipStream_t s) {
+  const int64_t blocks = (int64_t)a.G * ((2 * a.nL + kCapThreads - 1) / kCapThreads);
+  if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((cap_apply16_kernel<TT>), dim3((unsigned)blocks), dim3(kCapThreads), 0, s,
+                     reinterpret_cast<const TT*>(a.T0), reinterpret_cast<const TT*>(a.T1), a.in, a.out, a);
+  return hipGetLastError();
+}
+
+template <typename TT, int TM, int TN, int RG>
 hipError_t launch_nbc(const CapArgs& a, hipStream_t s) {
-  constexpr int RPB = 64 * 4 * (4 / RG);
+  constexpr int RPB = 64 * TM * (4 / RG);
   const int64_t blocks = (int64_t)a.G * ((2 * a.nL + RPB - 1) / RPB);
   if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((cap_apply_kernel<TT, TN, RG>), dim3((unsigned)blocks), dim3(kCapThreads), 0, s,
+  hipLaunchKernelGGL((cap_apply_kernel<TT, TM, TN, RG>), dim3((unsigned)blocks), dim3(kCapThreads), 0, s,
                      reinterpret_cast<const TT*>(a.T0), reinterpret_cast<const TT*>(a.T1), a.in, a.out, a);
   return hipGetLastError();
 }
 
 template <typename TT>
 hipError_t launch_typed(const CapArgs& a, hipStream_t s) {
-  // TN right-hand sides per wave (the smallest power of two covering nb, at
-  // most 4) and RG waves sharing rows: up to 16 right-hand sides per pass
-  // over the table, more in further passes
-  if (a.nb <= 1) return launch_nbc<TT, 1, 1>(a, s);
-  if (a.nb <= 2) return launch_nbc<TT, 2, 1>(a, s);
-  if (a.nb <= 4) return launch_nbc<TT, 4, 1>(a, s);
-  if (a.nb <= 8) return launch_nbc<TT, 4, 2>(a, s);
-  return launch_nbc<TT, 4, 4>(a, s);
+  // Up to 8 right-hand sides: TN per wave (the smallest power of two
+  // covering nb, at most 4), 4 rows per lane, and RG waves sharing rows.
+  // More, with complex128 tables: cap_apply16_kernel (sharing rows, the
+  // waves fetched the table 1.7 times at 512^3 x 16; 2.56 -> 2.45 ms per
+  // launch).  With complex64 tables four waves sharing rows stay faster
+  // (1.78 against 2.31 ms per launch at 512^3 x 16: the LDS reads of the
+  // vectors outweigh the saved fetch).
+  if (a.nb <= 1) return launch_nbc<TT, 4, 1, 1>(a, s);
+  if (a.nb <= 2) return launch_nbc<TT, 4, 2, 1>(a, s);
+  if (a.nb <= 4) return launch_nbc<TT, 4, 4, 1>(a, s);
+  if (a.nb <= 8) return launch_nbc<TT, 4, 4, 2>(a, s);
+  if constexpr (sizeof(TT) == sizeof(double2)) return launch_16<TT>(a, s);
+  return launch_nbc<TT, 4, 4, 4>(a, s);
 }
 
 // dst[g][x'][r] = src[x'][g][r] (r < 2 nL), narrowed to complex64 if TT is.

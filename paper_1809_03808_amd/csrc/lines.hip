@@ -255,6 +255,7 @@ __device__ inline Aff scan_bwd(Aff v, int q, Aff* wbuf) {
 struct LineDev {
   int nb, nO, nI, nL, c, red, tile, ntiles, iters;
   int tl, tm;  // red == 0 with tm > 0: blocks take tiles of tl outer x tm inner modes
+  int xcd;     // with tiles: consecutive blocks of one XCD take consecutive tiles
   const double2* sO;
   const double2* sI;
   double2 sC;
@@ -336,12 +337,12 @@ __device__ inline bool decode_line(const LineDev& a, uint32_t g, uint32_t t, int
     m = (g - b * nmg) * (uint32_t)lpb + (uint32_t)sl;
     l = li;
     valid = li < nO && m < nI;
-  } else if (a.tm > 0) {   // tile t = (b, lt, mt), li - t*tile = (l - lt*tl)*tm + (m - mt*tm)
+  } else if (a.tm > 0) {   // tile t = (b, mt, lt), li - t*tile = (l - lt*tl)*tm + (m - mt*tm)
     const uint32_t nlt = (nO + (uint32_t)a.tl - 1) / (uint32_t)a.tl, nmt = (nI + (uint32_t)a.tm - 1) / (uint32_t)a.tm;
     const uint32_t idx = li - t * (uint32_t)a.tile;
-    const uint32_t bt = t / nmt, mt = t - bt * nmt;
-    b = bt / nlt;
-    const uint32_t lt = bt - b * nlt;
+    const uint32_t bm = t / nlt, lt = t - bm * nlt;
+    b = bm / nmt;
+    const uint32_t mt = bm - b * nmt;
     const uint32_t il = idx / (uint32_t)a.tm;
     l = lt * (uint32_t)a.tl + il;
     m = mt * (uint32_t)a.tm + (idx - il * (uint32_t)a.tm);
@@ -421,6 +422,12 @@ __global__ __launch_bounds__(NT) void lines_kernel(LineDev a) {
   if (a.red) {
     g = blk / (uint32_t)a.ntiles;
     t = blk - g * (uint32_t)a.ntiles;
+  } else if (a.xcd) {
+    // blocks are dealt to the 8 XCDs in turn: block 8k + x takes tile
+    // x ntiles/8 + k, so the blocks resident on one XCD work on
+    // consecutive tiles (outer-mode tiles fastest), which share the rank-2
+    // rows of their inner modes in that XCD's L2
+    t = (blk & 7u) * ((uint32_t)a.ntiles >> 3) + (blk >> 3);
   } else {
     t = blk;
   }
@@ -935,6 +942,7 @@ LineDev make_dev(const LineArgs& a, int P, int c) {
   d.unit_rhs = a.unit_rhs;
   d.tile = d.ntiles = d.iters = 0;
   d.tl = d.tm = 0;
+  d.xcd = 0;
   (void)P;
   return d;
 }
@@ -1001,6 +1009,7 @@ hipError_t launch_lines(LineArgs a, hipStream_t s) {
     const int64_t nt = (int64_t)a.nb * ((a.nO + a.tile_l - 1) / a.tile_l) * ((a.nI + a.tile_m - 1) / a.tile_m);
     if (nt > 0x7fffffffLL) return hipErrorInvalidValue;
     d.ntiles = (int)nt;
+    d.xcd = nt % 8 == 0 ? 1 : 0;
     blocks = nt;
   } else {
     const int64_t lines = (int64_t)a.nb * a.nO * a.nI;

@@ -2194,6 +2194,12 @@ int autotune_transform(helm_plan* p) {
 // its own workspace; the plans' pipelines are spread over side streams
 // inside one stream capture (longest first onto the least loaded stream), so
 // the graph has one independent branch per stream.
+// Most parallel branches (side streams) of a batch graph.
+constexpr int kBatchMaxBranches = 16;
+
+struct helm_batch;
+std::string batch_key(const helm_batch* b, const int* nrhs);
+
 struct helm_batch {
   std::vector<helm_plan*> plans;
   int max_nrhs = 1;
@@ -2211,6 +2217,7 @@ struct helm_batch {
   std::vector<uint64_t> kgen;  // workspace generation of each plan at capture
   hipStream_t kst = nullptr;
   std::vector<int> steps;  // refinement steps captured per plan
+  int branches = 0;        // parallel branches of the graph (side streams used), 0 = not chosen yet
   hipStream_t last = nullptr;
   void drop_graph() {
     if (exec) (void)hipGraphExecDestroy(exec);
@@ -2227,6 +2234,28 @@ struct helm_batch {
     if (fork) (void)hipEventDestroy(fork);
   }
 };
+
+// Tune-cache key of a batch: its size and a hash (FNV-1a) of every problem's
+// shape, precision and number of right-hand sides.
+std::string batch_key(const helm_batch* b, const int* nrhs) {
+  uint64_t hsh = 1469598103934665603ull;
+  auto mix = [&](int64_t v) {
+    for (int k = 0; k < 8; ++k) {
+      hsh ^= (uint64_t)(v >> (8 * k)) & 0xff;
+      hsh *= 1099511628211ull;
+    }
+  };
+  for (size_t i = 0; i < b->plans.size(); ++i) {
+    const helm_plan* p = b->plans[i];
+    mix(p->dim);
+    for (int j = 0; j < p->dim; ++j) mix(p->grid[j]);
+    mix(p->opt.precision);
+    mix(nrhs[i]);
+  }
+  char buf[96];
+  std::snprintf(buf, sizeof buf, "batch=%zu shapes=%016llx", b->plans.size(), (unsigned long long)hsh);
+  return buf;
+}
 
 extern "C" {
 
@@ -2615,7 +2644,7 @@ int helm_batch_create(helm_plan* const* plans, int count, int max_nrhs, helm_bat
     const int rc = ensure_workspace(p, max_nrhs, mixed, mixed || p->opt.check);
     if (rc) return rc;
   }
-  const int ns = std::min(count, 8);
+  const int ns = std::min(count, kBatchMaxBranches);
   for (int k = 0; k < ns; ++k) {
     hipStream_t s;
     hipEvent_t e;
@@ -2653,48 +2682,119 @@ int helm_batch_solve(helm_batch* b, const void* const* f, void* const* u, const 
       b->steps[i] = std::min(p->opt.max_iter, std::max(2, p->rep.iterations + 1));
     }
     if (hipStreamSynchronize(st) != hipSuccess) return HELM_EDEVICE;
-    // longest problems first, each onto the stream with the least work
+    // longest problems first, each onto the branch with the least work
     std::vector<int> order(n);
     for (int i = 0; i < n; ++i) order[i] = i;
     auto work = [&](int i) { return (double)npoints(b->plans[i]) * nrhs[i] * (1 + b->steps[i]); };
     std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return work(x) > work(y); });
-    const int ns = (int)b->side.size();
-    std::vector<double> load(ns, 0.0);
-    int rc = HELM_OK;
-    hipStream_t cs = b->cap;
-    if (hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed) != hipSuccess) return HELM_EDEVICE;
-    do {
-      if (hipEventRecord(b->fork, cs) != hipSuccess) { rc = HELM_EDEVICE; break; }
-      for (int k = 0; k < ns; ++k)
-        if (hipStreamWaitEvent(b->side[k], b->fork, 0) != hipSuccess) rc = HELM_EDEVICE;
-      if (rc) break;
-      for (int i : order) {
-        const int k = (int)(std::min_element(load.begin(), load.end()) - load.begin());
-        load[k] += work(i);
-        rc = enqueue_device_ir(b->plans[i], reinterpret_cast<const double2*>(f[i]),
-                               reinterpret_cast<double2*>(u[i]), nrhs[i], b->steps[i], b->steps[i], nullptr,
-                               b->side[k]);
+    // one graph with `ns` parallel branches (side streams)
+    auto capture = [&](int ns, hipGraph_t* out_g) -> int {
+      std::vector<double> load(ns, 0.0);
+      int rc = HELM_OK;
+      hipStream_t cs = b->cap;
+      if (hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed) != hipSuccess) return HELM_EDEVICE;
+      do {
+        if (hipEventRecord(b->fork, cs) != hipSuccess) { rc = HELM_EDEVICE; break; }
+        for (int k = 0; k < ns; ++k)
+          if (hipStreamWaitEvent(b->side[k], b->fork, 0) != hipSuccess) rc = HELM_EDEVICE;
         if (rc) break;
+        for (int i : order) {
+          const int k = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+          load[k] += work(i);
+          rc = enqueue_device_ir(b->plans[i], reinterpret_cast<const double2*>(f[i]),
+                                 reinterpret_cast<double2*>(u[i]), nrhs[i], b->steps[i], b->steps[i], nullptr,
+                                 b->side[k]);
+          if (rc) break;
+        }
+        // join every side stream back (also after an error, so that the
+        // capture can end)
+        for (int k = 0; k < ns; ++k) {
+          if (hipEventRecord(b->join[k], b->side[k]) != hipSuccess) rc = HELM_EDEVICE;
+          if (hipStreamWaitEvent(cs, b->join[k], 0) != hipSuccess) rc = HELM_EDEVICE;
+        }
+      } while (false);
+      hipGraph_t g = nullptr;
+      const hipError_t ce = hipStreamEndCapture(cs, &g);
+      if (rc || ce != hipSuccess || !g) {
+        if (g) (void)hipGraphDestroy(g);
+        (void)hipGetLastError();
+        return rc ? rc : HELM_EDEVICE;
       }
-      // join every side stream back (also after an error, so that the
-      // capture can end)
-      for (int k = 0; k < ns; ++k) {
-        if (hipEventRecord(b->join[k], b->side[k]) != hipSuccess) rc = HELM_EDEVICE;
-        if (hipStreamWaitEvent(cs, b->join[k], 0) != hipSuccess) rc = HELM_EDEVICE;
+      *out_g = g;
+      return HELM_OK;
+    };
+    // The number of branches is tuned: the candidates (all side streams, a
+    // half, a quarter) are captured and timed once each on these inputs (a
+    // launch is a whole solve, so the timing runs also leave u solved), the
+    // fastest is kept, and the choice is appended to the first plan's tune
+    // cache under the batch's shape signature and read back from there.
+    const int nmax = (int)b->side.size();
+    const std::string bkey = batch_key(b, nrhs);
+    const std::string& tpath = b->plans[0]->tune_path;
+    std::vector<int> cands;
+    int cached = 0;
+    if (b->branches > 0) {
+      cands.push_back(b->branches);
+    } else if (!tpath.empty() && tune_lookup(tpath, bkey, "branches=", &cached) && cached >= 1 && cached <= nmax) {
+      cands.push_back(cached);
+    } else {
+      for (int c = nmax; c >= 1 && (int)cands.size() < 3; c /= 2) cands.push_back(c);
+    }
+    std::vector<float> times;
+    int best = -1;
+    float best_ms = 0;
+    for (int c : cands) {
+      hipGraph_t g = nullptr;
+      int rc = capture(c, &g);
+      if (rc) return rc;
+      hipGraphExec_t ex = nullptr;
+      if (hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return HELM_EDEVICE;
       }
-    } while (false);
-    hipGraph_t g = nullptr;
-    const hipError_t ce = hipStreamEndCapture(cs, &g);
-    if (rc || ce != hipSuccess || !g) {
-      if (g) (void)hipGraphDestroy(g);
-      (void)hipGetLastError();
-      return rc ? rc : HELM_EDEVICE;
+      float ms = 0;
+      if (cands.size() > 1) {
+        hipEvent_t e0, e1;
+        if (hipEventCreate(&e0) != hipSuccess) rc = HELM_EDEVICE;
+        if (!rc && hipEventCreate(&e1) != hipSuccess) {
+          (void)hipEventDestroy(e0);
+          rc = HELM_EDEVICE;
+        }
+        if (!rc) {
+          if (hipEventRecord(e0, st) != hipSuccess || hipGraphLaunch(ex, st) != hipSuccess ||
+              hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+              hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+            rc = HELM_EDEVICE;
+          (void)hipEventDestroy(e0);
+          (void)hipEventDestroy(e1);
+        }
+      }
+      times.push_back(ms);
+      if (!rc && (best < 0 || ms < best_ms)) {
+        b->drop_graph();
+        b->graph = g;
+        b->exec = ex;
+        best = c;
+        best_ms = ms;
+      } else {
+        (void)hipGraphExecDestroy(ex);
+        (void)hipGraphDestroy(g);
+      }
+      if (rc) {
+        b->drop_graph();
+        return rc;
+      }
     }
-    b->graph = g;
-    if (hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0) != hipSuccess) {
-      b->drop_graph();
-      return HELM_EDEVICE;
+    if (cands.size() > 1 && !tpath.empty()) {
+      FILE* tf = std::fopen(tpath.c_str(), "a");
+      if (tf) {
+        std::fprintf(tf, "helm-tune %s branches=%d", bkey.c_str(), best);
+        for (size_t k = 0; k < cands.size(); ++k) std::fprintf(tf, " b%d_ms=%.6g", cands[k], times[k]);
+        std::fprintf(tf, "\n");
+        std::fclose(tf);
+      }
     }
+    b->branches = best;
     b->kf.assign(f, f + n);
     b->ku.assign(u, u + n);
     b->kn.assign(nrhs, nrhs + n);

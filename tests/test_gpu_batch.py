@@ -175,3 +175,36 @@ def test_batch_full_sides_by_oracle():
     batch.close()
     for p in plans:
         p.close()
+
+
+def test_batch_branches_tuned_and_cached(tmp_path):
+    """The batch graph's number of parallel branches is timed at capture and
+    written to the first plan's tune cache; a cached choice is used as it
+    stands (no new timing line), and either graph solves every problem."""
+    cache = tmp_path / "tune.txt"
+    probs = PROBLEMS[:4]
+
+    def run():
+        plans, fs, us, hosts = [], [], [], []
+        for i, (grid, omega, prec, k) in enumerate(probs):
+            plans.append(helm.Plan(grid, inputs.spacing(grid), omega, precision=prec, check=True,
+                                   tune_cache=str(cache)))
+            f = inputs.gaussian_batch(grid, [inputs.rhs_seed(6, i, r) for r in range(k)])
+            hosts.append(f)
+            fs.append(torch.from_numpy(f).cuda())
+            us.append(torch.empty_like(fs[-1]))
+        batch = helm.Batch(plans, max_nrhs=3)
+        batch.solve(fs, us)
+        for i, (grid, omega, prec, k) in enumerate(probs):
+            _check(i, grid, omega, prec, hosts[i], us[i].cpu().numpy(), batch.report(i))
+        return [ln for ln in cache.read_text().splitlines() if "branches=" in ln]
+
+    lines = run()
+    assert len(lines) == 1, lines
+    _say("tuned:", lines[0])
+    key = " ".join(lines[0].split()[1:3])
+    assert key.startswith("batch=4 shapes=")
+    with open(cache, "a") as fh:
+        fh.write(f"helm-tune {key} branches=1\n")
+    lines = run()
+    assert len(lines) == 2 and lines[-1].endswith("branches=1"), lines

@@ -311,6 +311,8 @@ TABLE_CASES = [
     ((3, 3, 513), 150.0, 0b111111, 2),  # 8 P + 1 rows
     ((6, 5, 300), 30.0, 0b111111, 17),  # padded lines; more than 16 right-hand sides
     ((33, 40, 9), 14.0, 0b111111, 3),   # mode-tiled storing launch
+    ((5, 7, 45), 20.0, 0b111111, 12),   # 9-16 right-hand sides: partial vector chunk and row block
+    ((4, 6, 200), 60.0, 0b111111, 16),  # 16 right-hand sides, two row blocks per group
 ]
 
 
