@@ -194,6 +194,12 @@ template <typename C> constexpr int tile_w(int L) {
   return pow2_floor((tile_bytes(L) / (L * (int)sizeof(C))) < kFftMaxW ? tile_bytes(L) / (L * (int)sizeof(C))
                                                                        : kFftMaxW);
 }
+// A second tile for the complex64 512-point pass, chosen per plan by the
+// tuner: 64 KB (16 columns, 128-byte row segments) with the same 1024
+// threads, so that two blocks share a compute unit and one block's loads
+// overlap the other's LDS stages.  WO = 0 is the default tile.
+template <int L, typename C, int WO> constexpr int tile_w_of() { return WO ? WO : tile_w<C>(L); }
+template <int L, typename C, int WO> constexpr int min_waves_of() { return WO ? 8 : 1; }
 
 // One Stockham stage of radix R with Ns points already combined.  Thread
 // tid of NT = threads_of(L) owns butterflies t = tid + q*NT, t -> (j = t / W,
@@ -306,9 +312,10 @@ __device__ inline void stages(const PassDev& p, C* sm, const void* in, void* out
   }
 }
 
-template <int L, typename C>
-__global__ __launch_bounds__(threads_of(L)) void fft_pass_kernel(PassDev p, const void* in, void* out) {
-  constexpr int W = tile_w<C>(L);
+template <int L, typename C, int WO = 0>
+__global__ __launch_bounds__(threads_of(L), (min_waves_of<L, C, WO>())) void fft_pass_kernel(PassDev p, const void* in,
+                                                                                            void* out) {
+  constexpr int W = tile_w_of<L, C, WO>();
   __shared__ C sm[nstages(L) > 1 ? L * W : 1];
   if (p.skip && *p.skip) return;
   const int64_t blk = blockIdx.x;
@@ -378,20 +385,24 @@ hipError_t launch_conv_typed(int L, const PassDev& p, int64_t O, const void* in,
   }
 }
 
-template <int L, typename C>
+template <int L, typename C, int WO = 0>
 hipError_t launch_L(const PassDev& p, int64_t O, const void* in, void* out, hipStream_t s) {
-  constexpr int W = tile_w<C>(L);
+  constexpr int W = tile_w_of<L, C, WO>();
   PassDev q = p;
   q.ntile = (p.I + W - 1) / W;
   const int64_t blocks = O * q.ntile;
   if (blocks <= 0) return hipSuccess;
   if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((fft_pass_kernel<L, C>), dim3((unsigned)blocks), dim3(threads_of(L)), 0, s, q, in, out);
+  hipLaunchKernelGGL((fft_pass_kernel<L, C, WO>), dim3((unsigned)blocks), dim3(threads_of(L)), 0, s, q, in, out);
   return hipGetLastError();
 }
 
 template <typename C>
-hipError_t launch_typed(int L, const PassDev& p, int64_t O, const void* in, void* out, hipStream_t s) {
+hipError_t launch_typed(int L, const PassDev& p, int64_t O, const void* in, void* out, hipStream_t s,
+                        int small_tile) {
+  if constexpr (sizeof(C) == sizeof(float2)) {
+    if (L == 512 && small_tile) return launch_L<512, C, 16>(p, O, in, out, s);
+  }
   switch (L) {
     case 2: return launch_L<2, C>(p, O, in, out, s);
     case 4: return launch_L<4, C>(p, O, in, out, s);
@@ -444,7 +455,8 @@ static PassDev make_pass_dev(const FftPass& f) {
 hipError_t launch_fft_pass(const FftPass& f, bool fp32, const void* in, void* out, hipStream_t s) {
   if (f.tw4 && f.tw4_mode == 0 && f.tw4_S <= 0) return hipErrorInvalidValue;
   const PassDev p = make_pass_dev(f);
-  return fp32 ? launch_typed<float2>(f.L, p, f.O, in, out, s) : launch_typed<double2>(f.L, p, f.O, in, out, s);
+  return fp32 ? launch_typed<float2>(f.L, p, f.O, in, out, s, f.small_tile)
+              : launch_typed<double2>(f.L, p, f.O, in, out, s, 0);
 }
 
 hipError_t launch_conv_pass(const FftPass& f, bool fp32, const void* in, void* out, hipStream_t s) {

@@ -149,6 +149,7 @@ struct helm_plan {
   int cap_fp32 = 0;  // tables in complex64 (mixed-precision plans)
   int cap_min_nb = 0;
   int red_layout = 2;  // layout of the line reductions over the outer modes (2 or 3)
+  int fft_small = 0;   // complex64 512-point passes take the 64 KB tile (tuned)
   double cap_ms[4] = {-1, -1, -1, -1};  // measured: lines at 1 and 16 RHS, tables at 1 and 16 RHS
   std::string tune_path;
   double tune_ms[2] = {-1.0, -1.0};  // measured FFT / dense solve times (AUTO)
@@ -461,6 +462,12 @@ int prepare_roots(helm_plan* p) {
 
 int pick_W(int L, int64_t, bool fp32) { return fft_tile_width(L, fp32); }
 
+// A transform pass with the plan's tile choice.
+FftPass with_tile(const helm_plan* p, FftPass f) {
+  f.small_tile = p->fft_small;
+  return f;
+}
+
 // Power-of-two DFT of length L along the axis of [O][L][S] data (S
 // contiguous): one pass for L <= 512, else the four-step split L = na * nb
 // (pass 1 writes `tmp`).  Per-mode complex multiplier `cmode`, real `scale`.
@@ -492,7 +499,7 @@ int run_pow2(helm_plan* p, int L, int na, int nb, int sign, bool fp32, const voi
     f.skip = skip ? skip : p->skip_cur;
     f.tw = fp32 ? r->f.p : r->d.p;
     const double by = (double)O * L * S * (esz_of(in_kind) + esz_of(out_kind));
-    HCHK(timed(p, fp32 ? K_FFT32 : K_FFT64, by, st, [&] { return launch_fft_pass(f, fp32, in, out, st); }));
+    HCHK(timed(p, fp32 ? K_FFT32 : K_FFT64, by, st, [&] { return launch_fft_pass(with_tile(p, f), fp32, in, out, st); }));
     return HELM_OK;
   }
   // four-step: L = na * nb, x = a + na b, k = c + nb d
@@ -520,7 +527,7 @@ int run_pow2(helm_plan* p, int L, int na, int nb, int sign, bool fp32, const voi
   f1.tw = fp32 ? r1->f.p : r1->d.p;
   f1.tw4 = fp32 ? rn->f.p : rn->d.p;
   const double by1 = (double)O * L * S * (esz_of(in_kind) + esz_of(tmp_kind));
-  HCHK(timed(p, fp32 ? K_FFT32 : K_FFT64, by1, st, [&] { return launch_fft_pass(f1, fp32, in, tmp, st); }));
+  HCHK(timed(p, fp32 ? K_FFT32 : K_FFT64, by1, st, [&] { return launch_fft_pass(with_tile(p, f1), fp32, in, tmp, st); }));
   FftPass f2;
   f2.L = na;
   radix_plan(na, f2);
@@ -543,7 +550,7 @@ int run_pow2(helm_plan* p, int L, int na, int nb, int sign, bool fp32, const voi
   f2.skip = skip ? skip : p->skip_cur;
   f2.tw = fp32 ? r2->f.p : r2->d.p;
   const double by2 = (double)O * L * S * (esz_of(tmp_kind) + esz_of(out_kind));
-  HCHK(timed(p, fp32 ? K_FFT32 : K_FFT64, by2, st, [&] { return launch_fft_pass(f2, fp32, tmp, out, st); }));
+  HCHK(timed(p, fp32 ? K_FFT32 : K_FFT64, by2, st, [&] { return launch_fft_pass(with_tile(p, f2), fp32, tmp, out, st); }));
   return HELM_OK;
 }
 
@@ -598,7 +605,7 @@ int run_fft(helm_plan* p, const PAxis& a, int sign, bool fp32, const void* in, i
     f.cmode = bhat;
     f.skip = sk;
     const double by1 = (double)O * S * ((double)n * esz_of(in_kind) + (double)M * esz_of(T));
-    HCHK(timed(p, K, by1, st, [&] { return launch_fft_pass(f, fp32, in, t1, st); }));
+    HCHK(timed(p, K, by1, st, [&] { return launch_fft_pass(with_tile(p, f), fp32, in, t1, st); }));
     FftPass g = f;
     g.in_so = M * S;
     g.out_so1 = n * S;
@@ -613,7 +620,7 @@ int run_fft(helm_plan* p, const PAxis& a, int sign, bool fp32, const void* in, i
     g.scale_c = scale_c / (double)M;
     g.accumulate = accumulate;
     const double by2 = (double)O * S * ((double)M * esz_of(T) + (double)n * esz_of(out_kind) * (accumulate ? 2 : 1));
-    HCHK(timed(p, K, by2, st, [&] { return launch_fft_pass(g, fp32, t1, out, st); }));
+    HCHK(timed(p, K, by2, st, [&] { return launch_fft_pass(with_tile(p, g), fp32, t1, out, st); }));
     return HELM_OK;
   }
   // four-step convolution, M = na * nb: x = a + na b, k = c + nb d
@@ -649,7 +656,7 @@ int run_fft(helm_plan* p, const PAxis& a, int sign, bool fp32, const void* in, i
   f1.chirp_S = S;
   f1.skip = sk;
   const double by1 = (double)O * S * ((double)n * esz_of(in_kind) + (double)M * esz_of(T));
-  HCHK(timed(p, K, by1, st, [&] { return launch_fft_pass(f1, fp32, in, t1, st); }));
+  HCHK(timed(p, K, by1, st, [&] { return launch_fft_pass(with_tile(p, f1), fp32, in, t1, st); }));
   // 2: per group c, length-na DFT over a, product with the transformed
   //    kernel at k = c + nb d, unscaled inverse over d, twiddle
   //    e^{+2 pi i c a / M}; in place
@@ -701,7 +708,7 @@ int run_fft(helm_plan* p, const PAxis& a, int sign, bool fp32, const void* in, i
   f3.accumulate = accumulate;
   f3.skip = sk;
   const double by3 = (double)O * S * ((double)M * esz_of(T) + (double)n * esz_of(out_kind) * (accumulate ? 2 : 1));
-  HCHK(timed(p, K, by3, st, [&] { return launch_fft_pass(f3, fp32, t1, out, st); }));
+  HCHK(timed(p, K, by3, st, [&] { return launch_fft_pass(with_tile(p, f3), fp32, t1, out, st); }));
   return HELM_OK;
 }
 
@@ -2074,6 +2081,75 @@ int tune_layout(helm_plan* p) {
   return HELM_OK;
 }
 
+// Tile of the complex64 512-point transform passes (mixed-precision plans
+// with such a pass along a power-of-two axis): the 128 KB tile (32 columns,
+// one block per compute unit) or the 64 KB one (16 columns, two blocks),
+// each timed on the forward transform along the first such axis over a
+// volume of the plan's shape; cached as "fft512=".
+int tune_fft_tile(helm_plan* p) {
+  if (p->opt.precision != HELM_PREC_MIXED) return HELM_OK;
+  int axis = -1;
+  for (int j = 0; j < p->nper && axis < 0; ++j) {
+    const PAxis& a = p->ax[j];
+    // (chirp-z axes keep the default: their passes use the solve's workspace)
+    const bool u512 = !a.blue && (a.n == 512 || a.na == 512 || a.nbp == 512);
+    if (u512) axis = j;
+  }
+  if (axis < 0) return HELM_OK;
+  const std::string key = tune_key(p);
+  int cached = -1;
+  if (!p->tune_path.empty() && tune_lookup(p->tune_path, key, "fft512=", &cached) && (cached == 0 || cached == 1)) {
+    p->fft_small = cached;
+    return HELM_OK;
+  }
+  int64_t N = 1;
+  for (int j = 0; j < p->dim; ++j) N *= p->grid[j];
+  int64_t O = 1, S = 1;
+  for (int j = 0; j < axis; ++j) O *= p->grid[j];
+  for (int j = axis + 1; j < p->dim; ++j) S *= p->grid[j];
+  const PAxis& A = p->ax[axis];
+  const int64_t len = A.n;
+  DevMem in, out, tmp;
+  HCHK(in.ensure((size_t)(N / A.n) * len * sizeof(float2)));
+  HCHK(out.ensure((size_t)(N / A.n) * len * sizeof(float2)));
+  HCHK(tmp.ensure((size_t)(N / A.n) * len * sizeof(float2)));
+  HCHK(hipMemset(in.p, 0x3c, in.bytes));  // finite values of order 1e-2
+  hipEvent_t e0, e1;
+  HCHK(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return HELM_EDEVICE;
+  }
+  int rc = HELM_OK;
+  double best[2] = {1e30, 1e30};
+  for (int v = 0; v < 2 && !rc; ++v) {
+    p->fft_small = v;
+    for (int rep = 0; rep < 4 && !rc; ++rep) {
+      float ms = 0;
+      if (hipEventRecord(e0, nullptr) != hipSuccess) rc = HELM_EDEVICE;
+      if (!rc) rc = run_fft(p, A, -1, true, in.p, ST_C64, out.p, ST_C64, O, S, nullptr, 1.0, 0, tmp.p, ST_C64,
+                            nullptr);
+      if (!rc && (hipEventRecord(e1, nullptr) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                  hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+        rc = HELM_EDEVICE;
+      if (!rc && rep > 0) best[v] = std::min(best[v], (double)ms);
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc) return rc;
+  p->fft_small = best[1] < best[0] ? 1 : 0;
+  if (!p->tune_path.empty()) {
+    FILE* f = std::fopen(p->tune_path.c_str(), "a");
+    if (f) {
+      std::fprintf(f, "helm-tune %s fft512=%d tile128k_ms=%.6g tile64k_ms=%.6g\n", key.c_str(), p->fft_small,
+                   best[0], best[1]);
+      std::fclose(f);
+    }
+  }
+  return HELM_OK;
+}
+
 // Builds the tables when they fit the budget and decides from which number
 // of right-hand sides solves use them (helm_options.boundary).
 int setup_boundary_tables(helm_plan* p) {
@@ -2530,6 +2606,10 @@ int setup_impl(int dim, const int64_t* grid, const double* h, double c, long dou
   if (want_tab) {
     const int brc = setup_boundary_tables(p.get());
     if (brc != HELM_OK) return brc;
+  }
+  if (tf != HELM_TRANSFORM_DENSE) {
+    const int frc = tune_fft_tile(p.get());
+    if (frc != HELM_OK) return frc;
   }
   if (prepare_roots(p.get()) != HELM_OK) return HELM_ENOMEM;
   if (hipHostMalloc(reinterpret_cast<void**>(&p->h_norms_pin), 2 * HELM_STATIC_MAX_RHS * sizeof(double),
