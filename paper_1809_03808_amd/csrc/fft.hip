@@ -329,6 +329,8 @@ __global__ __launch_bounds__(threads_of(L), (min_waves_of<L, C, WO>())) void fft
 // Chirp-z middle pass: forward DFT over the rows into LDS, multiplication by
 // the transformed kernel, conjugation, a second forward DFT, and the
 // conjugating epilogue: conj(DFT(conj(X))) is the unscaled inverse DFT.
+// With L the whole convolution length and the chirps folded into the first
+// load and the last store, it is the complete transform in one pass.
 template <int L, typename C>
 __global__ __launch_bounds__(threads_of(L)) void conv_pass_kernel(PassDev p, const void* in, void* out) {
   constexpr int W = tile_w<C>(L);
@@ -381,6 +383,12 @@ hipError_t launch_conv_typed(int L, const PassDev& p, int64_t O, const void* in,
     case 128: return launch_conv_L<128, C>(p, O, in, out, s);
     case 256: return launch_conv_L<256, C>(p, O, in, out, s);
     case 512: return launch_conv_L<512, C>(p, O, in, out, s);
+    // whole chirp-z convolutions in one pass (the plan's choice per axis)
+    case 576: return launch_conv_L<576, C>(p, O, in, out, s);
+    case 1152: return launch_conv_L<1152, C>(p, O, in, out, s);
+    case 2304: return launch_conv_L<2304, C>(p, O, in, out, s);
+    case 1024: return launch_conv_L<1024, C>(p, O, in, out, s);
+    case 2048: return launch_conv_L<2048, C>(p, O, in, out, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -91,6 +91,7 @@ struct PAxis {
   // convolution length M >= 2n - 1 (a power of two, or 9 * 2^j) split as
   // Mna * Mnbp (Mna = 9 in the second case).
   int blue = 0, M = 0, Mna = 0, Mnbp = 0;
+  int onepass = 0;  // the whole chirp-z convolution in one pass (tuned)
   DevMem btab;
   const void* chirp_d[2] = {nullptr, nullptr};  // w for sign -1, +1 (double2[n])
   const void* chirp_f[2] = {nullptr, nullptr};  // same in float2
@@ -580,6 +581,42 @@ int run_fft(helm_plan* p, const PAxis& a, int sign, bool fp32, const void* in, i
   const void* bhat = fp32 ? a.bhat_f[si] : a.bhat_d[si];
   const int* sk = skip ? skip : p->skip_cur;
   const int K = fp32 ? K_FFT32 : K_FFT64;
+  if (a.onepass) {
+    // one pass: the M-point DFT of the chirped rows (zero past n) in LDS,
+    // the product with the transformed kernel, the unscaled inverse DFT
+    // (conj(DFT(conj(.)))), rows < n stored with the chirp, the per-mode
+    // scale and 1/M
+    Roots* rf = get_roots(p, (int)M, -1);
+    if (!rf) return HELM_ENOMEM;
+    FftPass f;
+    f.L = (int)M;
+    radix_plan((int)M, f);
+    f.I = S;
+    f.O = O;
+    f.od = 1;
+    f.in_so = n * S;
+    f.in_sj = S;
+    f.out_so1 = n * S;
+    f.out_sk = S;
+    f.in_kind = in_kind;
+    f.out_kind = out_kind;
+    f.sign = -1;
+    f.tw = fp32 ? rf->f.p : rf->d.p;
+    f.cin = chirp;
+    f.cout = chirp;
+    f.chirp_n = n;
+    f.chirp_na = 1;
+    f.chirp_S = S;
+    f.cmode = bhat;
+    f.conj_out = 1;
+    f.scale = scale;
+    f.scale_c = scale_c / (double)M;
+    f.accumulate = accumulate;
+    f.skip = sk;
+    const double by = (double)O * S * n * (esz_of(in_kind) + esz_of(out_kind) * (accumulate ? 2 : 1));
+    HCHK(timed(p, K, by, st, [&] { return launch_conv_pass(f, fp32, in, out, st); }));
+    return HELM_OK;
+  }
   if (a.Mna <= 1) {
     Roots* rf = get_roots(p, (int)M, -1);
     Roots* ri = get_roots(p, (int)M, +1);
@@ -2150,6 +2187,83 @@ int tune_fft_tile(helm_plan* p) {
   return HELM_OK;
 }
 
+// Chirp-z transforms (axes whose length is not a power of two): the
+// convolution in two or three passes over the padded length M (row
+// segments of up to 32 columns) or in one pass with the whole M-point
+// transform in LDS (narrower tiles: 4 to 8 columns, but the padded rows
+// never reach memory).  Timed per such axis on a volume of the plan's shape
+// and precision; cached as "chirp<axis>=".
+bool onepass_length(int M) {
+  return M == 576 || M == 1152 || M == 2304 || M == 1024 || M == 2048 || (M >= 2 && M <= 512 && !(M & (M - 1)));
+}
+
+int tune_chirp(helm_plan* p) {
+  const bool fp32 = p->opt.precision == HELM_PREC_MIXED;
+  const int T = fp32 ? ST_C64 : ST_C128;
+  const size_t esz = fp32 ? sizeof(float2) : sizeof(double2);
+  const std::string key = tune_key(p);
+  int64_t N = 1;
+  for (int j = 0; j < p->dim; ++j) N *= p->grid[j];
+  for (int j = 0; j < p->nper; ++j) {
+    PAxis& A = p->ax[j];
+    if (!A.blue || !onepass_length(A.M)) continue;
+    char field[16];
+    std::snprintf(field, sizeof field, "chirp%d=", j);
+    int cached = -1;
+    if (!p->tune_path.empty() && tune_lookup(p->tune_path, key, field, &cached) && (cached == 0 || cached == 1)) {
+      A.onepass = cached;
+      continue;
+    }
+    int64_t O = 1, S = 1;
+    for (int i = 0; i < j; ++i) O *= p->grid[i];
+    for (int i = j + 1; i < p->dim; ++i) S *= p->grid[i];
+    DevMem in, out, t1;
+    HCHK(in.ensure((size_t)N * esz));
+    HCHK(out.ensure((size_t)N * esz));
+    HCHK(t1.ensure((size_t)O * A.M * S * esz));
+    HCHK(hipMemset(in.p, 0x3c, in.bytes));  // finite values
+    // the multi-pass form takes its padded rows from the plan's chirp buffer
+    std::swap(p->BT1.p, t1.p);
+    std::swap(p->BT1.bytes, t1.bytes);
+    hipEvent_t e0, e1;
+    int rc = hipEventCreate(&e0) == hipSuccess ? HELM_OK : HELM_EDEVICE;
+    if (!rc && hipEventCreate(&e1) != hipSuccess) {
+      (void)hipEventDestroy(e0);
+      rc = HELM_EDEVICE;
+    }
+    double best[2] = {1e30, 1e30};
+    if (!rc) {
+      for (int v = 0; v < 2 && !rc; ++v) {
+        A.onepass = v;
+        for (int rep = 0; rep < 4 && !rc; ++rep) {
+          float ms = 0;
+          if (hipEventRecord(e0, nullptr) != hipSuccess) rc = HELM_EDEVICE;
+          if (!rc) rc = run_fft(p, A, -1, fp32, in.p, T, out.p, T, O, S, nullptr, 1.0, 0, nullptr, T, nullptr);
+          if (!rc && (hipEventRecord(e1, nullptr) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                      hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+            rc = HELM_EDEVICE;
+          if (!rc && rep > 0) best[v] = std::min(best[v], (double)ms);
+        }
+      }
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+    }
+    std::swap(p->BT1.p, t1.p);
+    std::swap(p->BT1.bytes, t1.bytes);
+    if (rc) return rc;
+    A.onepass = best[1] < best[0] ? 1 : 0;
+    if (!p->tune_path.empty()) {
+      FILE* f = std::fopen(p->tune_path.c_str(), "a");
+      if (f) {
+        std::fprintf(f, "helm-tune %s %s%d multipass_ms=%.6g onepass_ms=%.6g\n", key.c_str(), field, A.onepass,
+                     best[0], best[1]);
+        std::fclose(f);
+      }
+    }
+  }
+  return HELM_OK;
+}
+
 // Builds the tables when they fit the budget and decides from which number
 // of right-hand sides solves use them (helm_options.boundary).
 int setup_boundary_tables(helm_plan* p) {
@@ -2610,6 +2724,8 @@ int setup_impl(int dim, const int64_t* grid, const double* h, double c, long dou
   if (tf != HELM_TRANSFORM_DENSE) {
     const int frc = tune_fft_tile(p.get());
     if (frc != HELM_OK) return frc;
+    const int crc = tune_chirp(p.get());
+    if (crc != HELM_OK) return crc;
   }
   if (prepare_roots(p.get()) != HELM_OK) return HELM_ENOMEM;
   if (hipHostMalloc(reinterpret_cast<void**>(&p->h_norms_pin), 2 * HELM_STATIC_MAX_RHS * sizeof(double),

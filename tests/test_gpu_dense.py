@@ -185,3 +185,45 @@ def test_fft_tile_decision_timed_cached_and_correct(grid, tmp_path):
         assert [ln for ln in forced.read_text().splitlines() if "fft512=" in ln] == [f"helm-tune {key} fft512={choice}"]
         res = fem.rel_residual(grid, h, omega, abc, u, f.reshape(2, -1))
         assert rep["status"] == 0 and np.max(res) <= 1e-10 and np.max(fem.rel_error(u, ref)) <= 1e-8
+
+
+@pytest.mark.parametrize("grid,prec", [
+    ((257, 33), helm.PREC_FP64), ((513, 17), helm.PREC_MIXED), ((1025, 9), helm.PREC_FP64),
+    ((300, 20), helm.PREC_MIXED), ((17, 513, 9), helm.PREC_FP64), ((129, 9, 7), helm.PREC_MIXED),
+    ((2049, 5), helm.PREC_FP64),
+])
+def test_chirp_pass_decision_timed_cached_and_correct(grid, prec, tmp_path):
+    """Chirp-z axes: the plan times the multi-pass and the one-pass
+    convolution and caches the choice per axis; either form, forced through
+    the cache, meets the oracle bar (FP64 error, mixed residual)."""
+    omega = 2 * np.pi * (max(grid) - 1) / 10
+    h = inputs.spacing(grid)
+    dim = len(grid)
+    abc = ((True, True),) * dim
+    f = inputs.gaussian_batch(grid, [81, 82])
+    ref = fem.solve(grid, h, omega, abc, f.reshape(2, -1))
+    key = f"dim={dim} grid={grid[0]}x{grid[1]}x{grid[2] if dim == 3 else 1} prec={prec}"
+    axes = [j for j in range(dim - 1) if grid[j] & (grid[j] - 1)]
+    cache = tmp_path / "tune.txt"
+    with helm.Plan(grid, h, omega, precision=prec, tune_cache=str(cache)) as plan:
+        pass
+    # (2049 nodes: the 4608-point convolution has no one-pass form, nothing is timed)
+    timed = [ln for ln in cache.read_text().splitlines() if " chirp" in ln] if cache.exists() else []
+    assert len(timed) == (0 if grid[0] == 2049 else len(axes)), timed
+    for choice in (0, 1):
+        forced = tmp_path / f"forced{choice}.txt"
+        forced.write_text("".join(f"helm-tune {key} chirp{j}={choice}\n" for j in axes))
+        with helm.Plan(grid, h, omega, precision=prec, tune_cache=str(forced)) as plan:
+            fd = torch.from_numpy(f).cuda()
+            ud = torch.empty_like(fd)
+            plan.solve(fd, ud)
+            rep = plan.report()
+            u = ud.cpu().numpy().reshape(2, -1)
+        # the chirp decisions were read, not timed
+        assert len([ln for ln in forced.read_text().splitlines() if " chirp" in ln]) == len(axes)
+        assert rep["status"] == 0
+        if prec == helm.PREC_FP64:
+            assert np.max(fem.rel_error(u, ref)) <= 1e-9
+        else:
+            assert np.max(fem.rel_residual(grid, h, omega, abc, u, f.reshape(2, -1))) <= 1e-10
+            assert np.max(fem.rel_error(u, ref)) <= 1e-8
