@@ -387,6 +387,7 @@ hipError_t launch_conv_typed(int L, const PassDev& p, int64_t O, const void* in,
     case 576: return launch_conv_L<576, C>(p, O, in, out, s);
     case 1152: return launch_conv_L<1152, C>(p, O, in, out, s);
     case 2304: return launch_conv_L<2304, C>(p, O, in, out, s);
+    case 4608: return launch_conv_L<4608, C>(p, O, in, out, s);
     case 1024: return launch_conv_L<1024, C>(p, O, in, out, s);
     case 2048: return launch_conv_L<2048, C>(p, O, in, out, s);
     default: return hipErrorInvalidValue;

@@ -2194,7 +2194,8 @@ int tune_fft_tile(helm_plan* p) {
 // never reach memory).  Timed per such axis on a volume of the plan's shape
 // and precision; cached as "chirp<axis>=".
 bool onepass_length(int M) {
-  return M == 576 || M == 1152 || M == 2304 || M == 1024 || M == 2048 || (M >= 2 && M <= 512 && !(M & (M - 1)));
+  return M == 576 || M == 1152 || M == 2304 || M == 4608 || M == 1024 || M == 2048 ||
+         (M >= 2 && M <= 512 && !(M & (M - 1)));
 }
 
 int tune_chirp(helm_plan* p) {

@@ -207,9 +207,8 @@ def test_chirp_pass_decision_timed_cached_and_correct(grid, prec, tmp_path):
     cache = tmp_path / "tune.txt"
     with helm.Plan(grid, h, omega, precision=prec, tune_cache=str(cache)) as plan:
         pass
-    # (2049 nodes: the 4608-point convolution has no one-pass form, nothing is timed)
-    timed = [ln for ln in cache.read_text().splitlines() if " chirp" in ln] if cache.exists() else []
-    assert len(timed) == (0 if grid[0] == 2049 else len(axes)), timed
+    timed = [ln for ln in cache.read_text().splitlines() if " chirp" in ln]
+    assert len(timed) == len(axes), timed
     for choice in (0, 1):
         forced = tmp_path / f"forced{choice}.txt"
         forced.write_text("".join(f"helm-tune {key} chirp{j}={choice}\n" for j in axes))
