@@ -86,13 +86,15 @@ def test_autotuner_decides_and_caches(tmp_path):
     assert rc == helm.HELM_OK and rep["transform"] in (helm.TRANSFORM_FFT, helm.TRANSFORM_DENSE)
     ref = fem.solve(grid, h, omega, _abc_tuple(2, 0b1111), f.reshape(1, -1))
     assert fem.rel_error(u.reshape(1, -1), ref)[0] <= 1e-9
-    lines = open(path).read().splitlines()
-    _say("  tune cache:", lines)
+    everything = open(path).read().splitlines()
+    _say("  tune cache:", everything)
+    # (the chirp-z axis of length 48 adds its own decision line)
+    lines = [ln for ln in everything if " transform=" in ln]
     assert len(lines) == 1 and lines[0].startswith("helm-tune dim=2 grid=48x40x1 prec=0 transform=")
-    # a second plan of the same shape takes the cached decision without timing
+    # a second plan of the same shape takes the cached decisions without timing
     rc2, rep2, u2, _ = _solve(grid, 60.0, 0b1111, f, helm.PREC_FP64, helm.TRANSFORM_AUTO, path)
     assert rc2 == helm.HELM_OK and rep2["transform"] == rep["transform"]
-    assert len(open(path).read().splitlines()) == 1
+    assert len(open(path).read().splitlines()) == len(everything)
     # a forced choice in the cache is honoured
     forced = helm.TRANSFORM_DENSE if rep["transform"] == helm.TRANSFORM_FFT else helm.TRANSFORM_FFT
     with open(path, "a") as fh:
@@ -152,8 +154,9 @@ def test_cached_schedule_decisions_are_honoured(tmp_path):
             err = fem.rel_error(u, ref)
             assert rep["boundary"] == want, (prec, nmin, rep)
             assert np.max(err) <= (1e-9 if prec == helm.PREC_FP64 else 1e-8)
-            # nothing was measured, so nothing was appended
-            assert len(cache.read_text().splitlines()) == 2
+            # nothing of these was measured, so nothing of these was appended
+            # (the chirp-z axes of lengths 12 and 10 add their own lines)
+            assert len([ln for ln in cache.read_text().splitlines() if " chirp" not in ln]) == 2
 
 
 @pytest.mark.parametrize("grid", [(512, 11), (3, 512, 5), (512, 3, 9)])
