@@ -973,15 +973,21 @@ int inner_solve(helm_plan* p, const Level& lv, const InnerIO& io, hipStream_t st
     s3.tile = tl;
     s3.ntiles = ntl;
     if (io.PO) {
-      // square mode tiles of about as many lines as the consecutive runs
-      // would have (so the launch keeps its number of blocks): the rank-2
-      // rows of either kind are then re-read once per tile row / column
-      // instead of once per outer mode
+      // mode tiles of e outer x e/2 inner modes, e chosen so that a tile has
+      // no more lines than the consecutive runs would have (the launch keeps
+      // its number of blocks): the rank-2 rows of an inner mode are then
+      // re-read once per tile instead of once per outer mode, and with the
+      // XCD-major tile order the blocks resident on one XCD share the rows
+      // of their inner-mode tile in L2 (512^3 x 16 storing launch: fetch 52
+      // GB untiled, 48 GB with 32 x 32 tiles, 39 GB with 32 x 16)
       int P, c, NT;
       lines_geometry(lv.nL, &P, &c, &NT);
       int e = 32;
-      while (e > 4 && (e * e > tl || e > lv.nO || e > lv.nI)) e /= 2;
-      if (e >= 8 && (e * e) % (NT / P) == 0) s3.tile_l = s3.tile_m = e;
+      while (e > 4 && (e * e / 2 > tl || e > lv.nO || e / 2 > lv.nI)) e /= 2;
+      if (e >= 8 && (e * e / 2) % (NT / P) == 0) {
+        s3.tile_l = e;
+        s3.tile_m = e / 2;
+      }
     }
   }
   const double by3 = (io.in ? elems * esz_of(io.in_kind) : 0.0) + (io.out ? elems * esz_of(io.out_kind) : 0.0);
