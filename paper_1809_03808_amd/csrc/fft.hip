@@ -11,6 +11,8 @@
 // reads global memory and the last stage writes it, so a pass touches HBM
 // exactly once each way.  Long axes are split into two passes (four-step:
 // n = n_a n_b, twiddle e^{-2 pi i a c/n} between the passes).
+#include <algorithm>
+
 #include "helm_internal.h"
 
 namespace helm {
@@ -208,9 +210,10 @@ template <int L, typename C, int WO> constexpr int min_waves_of() { return WO ? 
 // place in LDS.  The first stage reads global memory, the last writes it
 // (with the four-step twiddle, the per-mode scale and the optional
 // accumulation).
-template <int L, int W, int R, int Ns, bool FIRST, bool LAST, typename C, bool GIN = true, bool GOUT = true>
+template <int L, int W, int R, int Ns, bool FIRST, bool LAST, typename C, bool GIN = true, bool GOUT = true,
+          bool REG = false>
 __device__ inline void stage(const PassDev& p, C* sm, const void* in, void* out, int64_t o, int64_t i0,
-                             int64_t oq, int64_t orr, int64_t a4) {
+                             int64_t oq, int64_t orr, int64_t a4, const C* vin, int tid) {
   constexpr bool LOADG = FIRST && GIN;    // this stage reads global memory
   constexpr bool STOREG = LAST && GOUT;   // this stage writes global memory
   constexpr int LR = L / R;
@@ -218,7 +221,6 @@ __device__ inline void stage(const PassDev& p, C* sm, const void* in, void* out,
   constexpr int NT = threads_of(L);
   static_assert(NT % W == 0 && L * W * (int)sizeof(C) <= 160 * 1024, "tile does not fit the thread block or LDS");
   constexpr int NB = (NBF + NT - 1) / NT;
-  const int tid = threadIdx.x;
   const int w = tid % W;
   const int64_t col = i0 + w;
   const bool colok = col < p.I;
@@ -232,7 +234,9 @@ __device__ inline void stage(const PassDev& p, C* sm, const void* in, void* out,
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         const int row = j + r * LR;
-        if constexpr (LOADG) {
+        if constexpr (LOADG && REG) {
+          v[q][r] = vin[q * R + r];  // loaded by the caller
+        } else if constexpr (LOADG) {
           C x;
           x.x = 0;
           x.y = 0;
@@ -302,13 +306,15 @@ __device__ inline void stage(const PassDev& p, C* sm, const void* in, void* out,
   if constexpr (!STOREG) __syncthreads();
 }
 
-template <int L, int W, int S, int Ns, typename C, bool GIN = true, bool GOUT = true>
+template <int L, int W, int S, int Ns, typename C, bool GIN = true, bool GOUT = true, bool REG = false>
 __device__ inline void stages(const PassDev& p, C* sm, const void* in, void* out, int64_t o, int64_t i0,
-                              int64_t oq, int64_t orr, int64_t a4) {
+                              int64_t oq, int64_t orr, int64_t a4, const C* vin = nullptr,
+                              int tid = (int)threadIdx.x) {
   if constexpr (S < nstages(L)) {
     constexpr int R = radix_of(L, S);
-    stage<L, W, R, Ns, S == 0, S == nstages(L) - 1, C, GIN, GOUT>(p, sm, in, out, o, i0, oq, orr, a4);
-    stages<L, W, S + 1, Ns * R, C, GIN, GOUT>(p, sm, in, out, o, i0, oq, orr, a4);
+    stage<L, W, R, Ns, S == 0, S == nstages(L) - 1, C, GIN, GOUT, REG>(p, sm, in, out, o, i0, oq, orr, a4, vin,
+                                                                          tid);
+    stages<L, W, S + 1, Ns * R, C, GIN, GOUT, REG>(p, sm, in, out, o, i0, oq, orr, a4, vin, tid);
   }
 }
 
@@ -324,6 +330,105 @@ __global__ __launch_bounds__(threads_of(L), (min_waves_of<L, C, WO>())) void fft
   const int64_t oq = o / p.od, orr = o - oq * p.od;
   const int64_t a4 = p.tw4 ? (i0 + (int64_t)(threadIdx.x % W)) / p.tw4_S : 0;
   stages<L, W, 0, 1, C>(p, sm, in, out, o, i0, oq, orr, a4);
+}
+
+// Streaming form of the 512-point pass (the plan's tile choice 2): one
+// block per compute unit walks the tiles blk, blk + G, blk + 2G, ... and
+// issues the loads of its next tile's first-stage inputs into registers
+// right after the first stage of the current one, so each compute unit
+// keeps HBM reads in flight through the remaining LDS stages and the
+// stores.  (With one block per tile, a compute unit holding a single 128 KB
+// tile leaves HBM idle for the length of its LDS stages.)  The global
+// loads of a wave complete in issue order, so waiting for any load issued
+// after the prefetch would wait for the prefetch too: the stage twiddles
+// and the per-mode scale are therefore read from LDS copies made once per
+// block, and the loads are unconditional (columns past the end read column
+// 0 of the row, in bounds) and masked when the values are taken.  Inputs
+// in the compute precision; no chirp factors, per-mode multiplier,
+// conjugation or four-step twiddle, and od = 1 (single passes over the
+// axis; checked by the launcher and set here as constants, so that the
+// epilogue keeps only the scale).  The output kind and the accumulation
+// are template arguments, so that the stores are straight-line code and the
+// compiler's wait for the prefetched values at the top of the loop does not
+// also wait for the previous tile's stores.
+template <int L, typename C, bool OUT128, bool ACC>
+__global__ __launch_bounds__(threads_of(L), 1) void fft_stream_kernel(PassDev p0, const void* in, void* out,
+                                                                      int64_t ntot) {
+  constexpr int W = tile_w<C>(L);
+  constexpr int NT = threads_of(L);
+  constexpr int R0 = radix_of(L, 0);
+  constexpr int LR = L / R0;
+  constexpr int NB = LR * W / NT;
+  static_assert(NB * NT == LR * W, "the first stage's butterflies fill the block");
+  static_assert((L * W + L) * sizeof(C) + L * sizeof(double) <= 160 * 1024, "LDS");
+  __shared__ C sm[L * W];
+  __shared__ C twl[L];
+  __shared__ double scl[L];
+  if (p0.skip && *p0.skip) return;
+  const int tid = threadIdx.x;
+  const int w = tid % W;
+  const int64_t G = gridDim.x;
+  for (int e = tid; e < L; e += NT) {
+    twl[e] = reinterpret_cast<const C*>(p0.tw)[e];
+    scl[e] = p0.scale ? p0.scale[e] : 1.0;
+  }
+  PassDev p = p0;
+  p.cin = p.cout = p.cmode = p.tw4 = nullptr;
+  p.conj_out = 0;
+  p.od = 1;
+  p.out_kind = OUT128 ? ST_C128 : ST_C64;
+  p.acc = ACC ? 1 : 0;
+  p.tw = twl;
+  p.scale = scl;
+  C pre[NB * R0];
+  // Row r LR + j of a tile: the tile's base (uniform) plus the thread's
+  // 32-bit byte offset (j in_sj + w) sizeof(C) (the launcher checks that
+  // LR in_sj sizeof(C) < 2^31), so that only the thread offsets take
+  // vector registers besides the values.
+  uint32_t toff[NB];
+#pragma unroll
+  for (int q = 0; q < NB; ++q)
+    toff[q] = (uint32_t)(((tid + q * NT) / W) * p.in_sj + w) * (uint32_t)sizeof(C);
+  auto fetch = [&](int64_t tile) -> bool {
+    const int64_t o = tile / p.ntile;
+    const int64_t i0 = (tile - o * p.ntile) * W;
+    const bool ok = i0 + w < p.I;
+    const uint32_t msk = ok ? 0xffffffffu : 0u;
+    const char* base = reinterpret_cast<const char*>(reinterpret_cast<const C*>(in) + o * p.in_so + i0);
+#pragma unroll
+    for (int r = 0; r < R0; ++r) {
+      const char* br = base + (int64_t)r * LR * p.in_sj * (int64_t)sizeof(C);
+#pragma unroll
+      for (int q = 0; q < NB; ++q) pre[q * R0 + r] = *reinterpret_cast<const C*>(br + (toff[q] & msk));
+    }
+    return ok;
+  };
+  int64_t tile = blockIdx.x;
+  bool ok = tile < ntot ? fetch(tile) : false;
+  __syncthreads();  // the LDS copies of the tables
+  for (; tile < ntot; tile += G) {
+    C v[NB * R0];
+#pragma unroll
+    for (int k = 0; k < NB * R0; ++k) {
+      v[k] = pre[k];
+      if (!ok) v[k].x = v[k].y = 0;
+    }
+    const int64_t o = tile / p.ntile;
+    const int64_t i0 = (tile - o * p.ntile) * W;
+    // The output row offsets (multiples of out_sk) and the LDS addresses
+    // of the stages are the same for every tile; empty asm statements make
+    // the stride and the thread index new to the compiler in each
+    // iteration, so it recomputes those per tile instead of keeping all of
+    // them in registers across the loop.
+    int64_t osk = p0.out_sk;
+    int tl = tid;
+    asm volatile("" : "+s"(osk), "+v"(tl));
+    p.out_sk = osk;
+    // first stage from the registers into LDS, then the next tile's loads
+    stage<L, W, R0, 1, true, nstages(L) == 1, C, true, true, true>(p, sm, in, out, o, i0, o, 0, 0, v, tl);
+    if (tile + G < ntot) ok = fetch(tile + G);
+    stages<L, W, 1, R0, C, true, true, true>(p, sm, in, out, o, i0, o, 0, 0, v, tl);
+  }
 }
 
 // Chirp-z middle pass: forward DFT over the rows into LDS, multiplication by
@@ -406,11 +511,49 @@ hipError_t launch_L(const PassDev& p, int64_t O, const void* in, void* out, hipS
   return hipGetLastError();
 }
 
+// Compute units of the current device, for the streaming pass's grid.
+int compute_units() {
+  static int cu[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  if (cu[dev] <= 0) {
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) n = 256;
+    cu[dev] = n;
+  }
+  return cu[dev];
+}
+
+template <int L, typename C>
+hipError_t launch_stream_L(const PassDev& p, int64_t O, const void* in, void* out, hipStream_t s) {
+  constexpr int W = tile_w<C>(L);
+  PassDev q = p;
+  q.ntile = (p.I + W - 1) / W;
+  const int64_t ntot = O * q.ntile;
+  if (ntot <= 0) return hipSuccess;
+  const int64_t blocks = std::min<int64_t>(ntot, compute_units());
+  const dim3 g((unsigned)blocks), b(threads_of(L));
+  const bool o128 = p.out_kind == ST_C128;
+  if (o128 && p.acc) hipLaunchKernelGGL((fft_stream_kernel<L, C, true, true>), g, b, 0, s, q, in, out, ntot);
+  else if (o128) hipLaunchKernelGGL((fft_stream_kernel<L, C, true, false>), g, b, 0, s, q, in, out, ntot);
+  else if (p.acc) hipLaunchKernelGGL((fft_stream_kernel<L, C, false, true>), g, b, 0, s, q, in, out, ntot);
+  else hipLaunchKernelGGL((fft_stream_kernel<L, C, false, false>), g, b, 0, s, q, in, out, ntot);
+  return hipGetLastError();
+}
+
+// small_tile: 0 the default tile, 1 the 64 KB complex64 tile, 2 the
+// streaming pass (512 points; other passes and inputs that it does not
+// take fall back to the default).
 template <typename C>
 hipError_t launch_typed(int L, const PassDev& p, int64_t O, const void* in, void* out, hipStream_t s,
                         int small_tile) {
+  constexpr int kind = sizeof(C) == sizeof(float2) ? ST_C64 : ST_C128;
+  if (L == 512 && small_tile == 2 && !p.cin && !p.cout && !p.cmode && !p.tw4 && !p.conj_out && p.od == 1 &&
+      p.in_kind == kind &&
+      (int64_t)(L / radix_of(L, 0)) * p.in_sj * (int64_t)sizeof(C) < 0x7fffffffLL)
+    return launch_stream_L<512, C>(p, O, in, out, s);
   if constexpr (sizeof(C) == sizeof(float2)) {
-    if (L == 512 && small_tile) return launch_L<512, C, 16>(p, O, in, out, s);
+    if (L == 512 && small_tile == 1) return launch_L<512, C, 16>(p, O, in, out, s);
   }
   switch (L) {
     case 2: return launch_L<2, C>(p, O, in, out, s);
@@ -465,7 +608,7 @@ hipError_t launch_fft_pass(const FftPass& f, bool fp32, const void* in, void* ou
   if (f.tw4 && f.tw4_mode == 0 && f.tw4_S <= 0) return hipErrorInvalidValue;
   const PassDev p = make_pass_dev(f);
   return fp32 ? launch_typed<float2>(f.L, p, f.O, in, out, s, f.small_tile)
-              : launch_typed<double2>(f.L, p, f.O, in, out, s, 0);
+              : launch_typed<double2>(f.L, p, f.O, in, out, s, f.small_tile);
 }
 
 hipError_t launch_conv_pass(const FftPass& f, bool fp32, const void* in, void* out, hipStream_t s) {

@@ -93,7 +93,7 @@ struct FftPass {
   int64_t tw4_S = 0;  // 0: no four-step twiddle
   int tw4_n = 0;
   int W = 0;          // inner columns per workgroup
-  int small_tile = 0; // complex64 512-point passes: 64 KB tiles (16 columns, two blocks per compute unit)
+  int small_tile = 0; // 512-point passes: 1 the 64 KB complex64 tile (two blocks per compute unit), 2 streaming
   int in_kind = ST_C128, out_kind = ST_C128;
   int accumulate = 0;
   int sign = -1;      // -1 forward (e^{-2 pi i ...}), +1 inverse

@@ -150,7 +150,7 @@ struct helm_plan {
   int cap_fp32 = 0;  // tables in complex64 (mixed-precision plans)
   int cap_min_nb = 0;
   int red_layout = 2;  // layout of the line reductions over the outer modes (2 or 3)
-  int fft_small = 0;   // complex64 512-point passes take the 64 KB tile (tuned)
+  int fft_small = 0;   // 512-point passes: 0 the 128 KB tile, 1 the 64 KB complex64 tile, 2 streaming (tuned)
   double cap_ms[4] = {-1, -1, -1, -1};  // measured: lines at 1 and 16 RHS, tables at 1 and 16 RHS
   std::string tune_path;
   double tune_ms[2] = {-1.0, -1.0};  // measured FFT / dense solve times (AUTO)
@@ -2130,7 +2130,7 @@ int tune_layout(helm_plan* p) {
 // each timed on the forward transform along the first such axis over a
 // volume of the plan's shape; cached as "fft512=".
 int tune_fft_tile(helm_plan* p) {
-  if (p->opt.precision != HELM_PREC_MIXED) return HELM_OK;
+  const bool fp32 = p->opt.precision == HELM_PREC_MIXED;
   int axis = -1;
   for (int j = 0; j < p->nper && axis < 0; ++j) {
     const PAxis& a = p->ax[j];
@@ -2139,9 +2139,14 @@ int tune_fft_tile(helm_plan* p) {
     if (u512) axis = j;
   }
   if (axis < 0) return HELM_OK;
+  // candidates: 0 the 128 KB tile, 1 the 64 KB complex64 tile, 2 the
+  // streaming pass (128 KB tiles, next tile's loads in flight)
+  const int nv = 3;
+  const bool cand[3] = {true, fp32, true};
   const std::string key = tune_key(p);
   int cached = -1;
-  if (!p->tune_path.empty() && tune_lookup(p->tune_path, key, "fft512=", &cached) && (cached == 0 || cached == 1)) {
+  if (!p->tune_path.empty() && tune_lookup(p->tune_path, key, "fft512=", &cached) && cached >= 0 && cached < nv &&
+      cand[cached]) {
     p->fft_small = cached;
     return HELM_OK;
   }
@@ -2151,12 +2156,13 @@ int tune_fft_tile(helm_plan* p) {
   for (int j = 0; j < axis; ++j) O *= p->grid[j];
   for (int j = axis + 1; j < p->dim; ++j) S *= p->grid[j];
   const PAxis& A = p->ax[axis];
-  const int64_t len = A.n;
+  const int T = fp32 ? ST_C64 : ST_C128;
+  const size_t bytes = (size_t)N * (fp32 ? sizeof(float2) : sizeof(double2));
   DevMem in, out, tmp;
-  HCHK(in.ensure((size_t)(N / A.n) * len * sizeof(float2)));
-  HCHK(out.ensure((size_t)(N / A.n) * len * sizeof(float2)));
-  HCHK(tmp.ensure((size_t)(N / A.n) * len * sizeof(float2)));
-  HCHK(hipMemset(in.p, 0x3c, in.bytes));  // finite values of order 1e-2
+  HCHK(in.ensure(bytes));
+  HCHK(out.ensure(bytes));
+  HCHK(tmp.ensure(bytes));
+  HCHK(hipMemset(in.p, 0x3c, in.bytes));  // finite values (order 1e-2 in FP32, 1e-18 in FP64)
   hipEvent_t e0, e1;
   HCHK(hipEventCreate(&e0));
   if (hipEventCreate(&e1) != hipSuccess) {
@@ -2164,14 +2170,14 @@ int tune_fft_tile(helm_plan* p) {
     return HELM_EDEVICE;
   }
   int rc = HELM_OK;
-  double best[2] = {1e30, 1e30};
-  for (int v = 0; v < 2 && !rc; ++v) {
+  double best[3] = {1e30, 1e30, 1e30};
+  for (int v = 0; v < nv && !rc; ++v) {
+    if (!cand[v]) continue;
     p->fft_small = v;
     for (int rep = 0; rep < 4 && !rc; ++rep) {
       float ms = 0;
       if (hipEventRecord(e0, nullptr) != hipSuccess) rc = HELM_EDEVICE;
-      if (!rc) rc = run_fft(p, A, -1, true, in.p, ST_C64, out.p, ST_C64, O, S, nullptr, 1.0, 0, tmp.p, ST_C64,
-                            nullptr);
+      if (!rc) rc = run_fft(p, A, -1, fp32, in.p, T, out.p, T, O, S, nullptr, 1.0, 0, tmp.p, T, nullptr);
       if (!rc && (hipEventRecord(e1, nullptr) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
                   hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
         rc = HELM_EDEVICE;
@@ -2181,12 +2187,15 @@ int tune_fft_tile(helm_plan* p) {
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (rc) return rc;
-  p->fft_small = best[1] < best[0] ? 1 : 0;
+  int pick = 0;
+  for (int v = 1; v < nv; ++v)
+    if (cand[v] && best[v] < best[pick]) pick = v;
+  p->fft_small = pick;
   if (!p->tune_path.empty()) {
     FILE* f = std::fopen(p->tune_path.c_str(), "a");
     if (f) {
-      std::fprintf(f, "helm-tune %s fft512=%d tile128k_ms=%.6g tile64k_ms=%.6g\n", key.c_str(), p->fft_small,
-                   best[0], best[1]);
+      std::fprintf(f, "helm-tune %s fft512=%d tile128k_ms=%.6g tile64k_ms=%.6g stream_ms=%.6g\n", key.c_str(), pick,
+                   best[0], cand[1] ? best[1] : -1.0, best[2]);
       std::fclose(f);
     }
   }

@@ -159,35 +159,44 @@ def test_cached_schedule_decisions_are_honoured(tmp_path):
             assert len([ln for ln in cache.read_text().splitlines() if " chirp" not in ln]) == 2
 
 
+@pytest.mark.parametrize("prec", [helm.PREC_MIXED, helm.PREC_FP64])
 @pytest.mark.parametrize("grid", [(512, 11), (3, 512, 5), (512, 3, 9)])
-def test_fft_tile_decision_timed_cached_and_correct(grid, tmp_path):
-    """Mixed-precision plans with a 512-point pass time the two tiles of that
-    pass once and cache the choice; either tile, forced through the cache,
-    meets the oracle bar."""
+def test_fft_tile_decision_timed_cached_and_correct(grid, prec, tmp_path):
+    """Plans with a 512-point pass time its forms once (the 128 KB tile, the
+    64 KB complex64 tile, the streaming pass) and cache the choice; each
+    form, forced through the cache, meets the oracle bar (the plain FP64
+    solve without refinement)."""
     omega = 2 * np.pi * (max(grid) - 1) / 12
     h = inputs.spacing(grid)
     dim = len(grid)
     abc = ((True, True),) * dim
     f = inputs.gaussian_batch(grid, [91, 92])
     ref = fem.solve(grid, h, omega, abc, f.reshape(2, -1))
-    key = f"dim={dim} grid={grid[0]}x{grid[1]}x{grid[2] if dim == 3 else 1} prec={helm.PREC_MIXED}"
+    key = f"dim={dim} grid={grid[0]}x{grid[1]}x{grid[2] if dim == 3 else 1} prec={prec}"
     cache = tmp_path / "tune.txt"
-    with helm.Plan(grid, h, omega, precision=helm.PREC_MIXED, tune_cache=str(cache)) as plan:
+    with helm.Plan(grid, h, omega, precision=prec, tune_cache=str(cache)) as plan:
         pass
     lines = [ln for ln in cache.read_text().splitlines() if "fft512=" in ln]
     assert len(lines) == 1 and lines[0].startswith(f"helm-tune {key} fft512="), lines
-    for choice in (0, 1):
+    assert "stream_ms=" in lines[0]
+    mixed = prec == helm.PREC_MIXED
+    for choice in ((0, 1, 2) if mixed else (0, 2)):
         forced = tmp_path / f"forced{choice}.txt"
         forced.write_text(f"helm-tune {key} fft512={choice}\n")
-        with helm.Plan(grid, h, omega, precision=helm.PREC_MIXED, tune_cache=str(forced)) as plan:
+        with helm.Plan(grid, h, omega, precision=prec, check=mixed, tune_cache=str(forced)) as plan:
             fd = torch.from_numpy(f).cuda()
             ud = torch.empty_like(fd)
             plan.solve(fd, ud)
             rep = plan.report()
             u = ud.cpu().numpy().reshape(2, -1)
         assert [ln for ln in forced.read_text().splitlines() if "fft512=" in ln] == [f"helm-tune {key} fft512={choice}"]
-        res = fem.rel_residual(grid, h, omega, abc, u, f.reshape(2, -1))
-        assert rep["status"] == 0 and np.max(res) <= 1e-10 and np.max(fem.rel_error(u, ref)) <= 1e-8
+        err = fem.rel_error(u, ref)
+        assert rep["status"] == 0
+        if mixed:
+            res = fem.rel_residual(grid, h, omega, abc, u, f.reshape(2, -1))
+            assert np.max(res) <= 1e-10 and np.max(err) <= 1e-8
+        else:
+            assert rep["iterations"] == 0 and np.max(err) <= 1e-9
 
 
 @pytest.mark.parametrize("grid,prec", [
