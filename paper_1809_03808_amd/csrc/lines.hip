@@ -650,154 +650,89 @@ __global__ __launch_bounds__(NT) void lines_kernel(LineDev a) {
       }
     }
 
-    // reciprocal pivot entering the lane's chunk (zero for the first lane)
+    // ---- 1. pivots and forward composition --------------------------------
+    // Reciprocal pivots: the chunk's entering value from the plan's factor
+    // table, then the Thomas recurrence p_x = d_x - e^2 / p_{x-1}.
+    // Forward substitution z_x = f_x z_{x-1} + d_x, f_x = -e / p_{x-1}: the
+    // lane composes its rows into one affine map.
     const double2 ip_in = (EARLY || EARLY_SP) ? eip : (q > 0 ? a.piv[(int64_t)(l * a.nI + m) * P + q] : make_double2(0, 0));
-    double2 yx = make_double2(0, 0);  // y of the extra row (XR, last lane)
-    if constexpr (EXACT) {
-      // ---- 1. pivots and the scaled forward substitution -----------------
-      // With h_x = w_x / p_x for Thomas' forward values w_x and the
-      // multipliers g_x = -e / p_x,
-      //   h_x = g_x h_{x-1} + r_x / p_x,     y_x = g_x y_{x+1} + h_x:
-      // every row of an exact line is coupled to both neighbours (the end
-      // rows' missing neighbour has the value zero), so the forward and the
-      // backward recurrence take the same multipliers and the two chunk maps
-      // the same product of them.  The lane composes its rows' forward maps,
-      // keeping r_x / p_x in z and g_x in its LDS slots.  Reciprocal pivots:
-      // the chunk's entering value from the plan's factor table, then the
-      // Thomas recurrence p_x = d_x - e^2 / p_{x-1}.
-      Aff A;
+    Aff A = aff_ident();
+    double2 ipp_last;  // 1/p of the chunk's last row
+    {
       double2 ipp = ip_in;
 #pragma unroll
-      for (int j = 0; j < C; ++j) {
-        double2 pv = (j == 0 && q == 0) ? rc.dlo : ((!XR && j == C - 1 && q == P - 1) ? rc.dhi : rc.dint);
-        pv = cfms(rc.off2, ipp, pv);  // ipp = 0 at x = 0
-        ipp = crcp_fast(pv);
-        const double2 gx = cmul(moff, ipp);
-        const double2 G = cmul(ipp, z[j]);
-        if (j == 0) {
-          A.f = gx;
-          A.g = G;
-        } else {
-          A.f = cmul(gx, A.f);
-          A.g = cfma(gx, A.g, G);
+      for (int j = 0; j < kCMax; ++j) {
+        if (in_chunk(j)) {
+          const int x = x0 + j;
+          double2 f = cmul(moff, ipp);
+          if (!EXACT && !has_e(x, nL)) f = make_double2(0, 0);
+          A.f = cmul(f, A.f);
+          A.g = cfma(f, A.g, z[j]);
+          double2 pv;
+          if (EXACT) {
+            pv = (j == 0 && q == 0) ? rc.dlo : ((!XR && j == C - 1 && q == P - 1) ? rc.dhi : rc.dint);
+            pv = cfms(rc.off2, ipp, pv);  // ipp = 0 at x = 0
+            ipp = crcp_fast(pv);
+          } else {
+            pv = diag_of(rc, x, nL);
+            if (has_e(x, nL)) pv = cfms(rc.off2, ipp, pv);
+            ipp = x < nL ? crcp_fast(pv) : make_double2(1, 0);
+          }
+          S[slot_of(j)] = ipp;
         }
-        z[j] = G;
-        S[slot_of(j)] = gx;
       }
-      const Aff Ein = scan_fwd<P>(A, q, wbuf[0]);
+      ipp_last = ipp;
+    }
+    const Aff Ein = scan_fwd<P>(A, q, wbuf[0]);
 
-      // ---- 2. forward values h -------------------------------------------
-      double2 hp = Ein.g;
+    // ---- 2. forward values, scaled for the back substitution --------------
+    // h_x = z_x / p_x; the lane's slots now take the backward multipliers
+    // g_x = -e / p_x (zero where row x + 1 is past the end of the line).
+    double2 yx = make_double2(0, 0);  // y of the extra row (XR, last lane)
+    {
+      double2 zp = Ein.g;
+      double2 mp = cmul(moff, ip_in);
 #pragma unroll
-      for (int j = 0; j < C; ++j) {
-        hp = cfma(S[slot_of(j)], hp, z[j]);
-        z[j] = hp;
+      for (int j = 0; j < kCMax; ++j) {
+        if (in_chunk(j)) {
+          const int x = x0 + j;
+          const double2 f = (EXACT || has_e(x, nL)) ? mp : make_double2(0, 0);
+          zp = cfma(f, zp, z[j]);
+          const double2 ipj = S[slot_of(j)];
+          z[j] = cmul(zp, ipj);
+          mp = cmul(moff, ipj);
+          S[slot_of(j)] = (EXACT || has_e(x + 1, nL)) ? mp : make_double2(0, 0);
+        }
       }
       if (XR && last) {
-        // extra row: h = (r - e h_{nL-2}) / p, p = d_hi - e^2 / p_{nL-2}; y = h
-        yx = cmul(crcp_fast(cfms(rc.off2, ipp, rc.dhi)), cfma(moff, hp, xrhs));
+        // extra row: w = r + (-e / p_{nL-2}) w_{nL-2}, p = d_hi - e^2 / p_{nL-2}
+        const double2 wx = cfma(cmul(moff, ipp_last), zp, xrhs);
+        yx = cmul(wx, crcp_fast(cfms(rc.off2, ipp_last, rc.dhi)));
       }
+    }
 
-      // ---- 3. back substitution: composition, scan, values ---------------
-      Aff B;
-      B.f = A.f;
-      B.g = z[C - 1];
+    // ---- 3. back substitution y_x = g_x y_{x+1} + h_x: composition, scan ---
+    Aff B = aff_ident();
 #pragma unroll
-      for (int j = C - 2; j >= 0; --j) B.g = cfma(S[slot_of(j)], B.g, z[j]);
-      if (XR && last) {  // the value above the chunk is known: a constant map
-        B.g = cfma(B.f, yx, B.g);
-        B.f = make_double2(0, 0);
+    for (int j = kCMax - 1; j >= 0; --j) {
+      if (in_chunk(j)) {
+        const double2 gx = S[slot_of(j)];
+        B.f = cmul(gx, B.f);
+        B.g = cfma(gx, B.g, z[j]);
       }
-      const Aff Bin = scan_bwd<P>(B, q, wbuf[1]);
+    }
+    if (XR && last) {  // the value above the chunk is known: a constant map
+      B.g = cfma(B.f, yx, B.g);
+      B.f = make_double2(0, 0);
+    }
+    const Aff Bin = scan_bwd<P>(B, q, wbuf[1]);
+    {
       double2 ynext = (XR && last) ? yx : Bin.g;
-#pragma unroll
-      for (int j = C - 1; j >= 0; --j) {
-        ynext = cfma(S[slot_of(j)], ynext, z[j]);
-        z[j] = ynext;
-      }
-    } else {
-      // ---- 1. pivots and forward composition --------------------------------
-      // Reciprocal pivots: the chunk's entering value from the plan's factor
-      // table, then the Thomas recurrence p_x = d_x - e^2 / p_{x-1}.
-      // Forward substitution z_x = f_x z_{x-1} + d_x, f_x = -e / p_{x-1}: the
-      // lane composes its rows into one affine map.
-      Aff A = aff_ident();
-      double2 ipp_last;  // 1/p of the chunk's last row
-      {
-        double2 ipp = ip_in;
-#pragma unroll
-        for (int j = 0; j < kCMax; ++j) {
-          if (in_chunk(j)) {
-            const int x = x0 + j;
-            double2 f = cmul(moff, ipp);
-            if (!EXACT && !has_e(x, nL)) f = make_double2(0, 0);
-            A.f = cmul(f, A.f);
-            A.g = cfma(f, A.g, z[j]);
-            double2 pv;
-            if (EXACT) {
-              pv = (j == 0 && q == 0) ? rc.dlo : ((!XR && j == C - 1 && q == P - 1) ? rc.dhi : rc.dint);
-              pv = cfms(rc.off2, ipp, pv);  // ipp = 0 at x = 0
-              ipp = crcp_fast(pv);
-            } else {
-              pv = diag_of(rc, x, nL);
-              if (has_e(x, nL)) pv = cfms(rc.off2, ipp, pv);
-              ipp = x < nL ? crcp_fast(pv) : make_double2(1, 0);
-            }
-            S[slot_of(j)] = ipp;
-          }
-        }
-        ipp_last = ipp;
-      }
-      const Aff Ein = scan_fwd<P>(A, q, wbuf[0]);
-
-      // ---- 2. forward values, scaled for the back substitution --------------
-      // h_x = z_x / p_x; the lane's slots now take the backward multipliers
-      // g_x = -e / p_x (zero where row x + 1 is past the end of the line).
-      {
-        double2 zp = Ein.g;
-        double2 mp = cmul(moff, ip_in);
-#pragma unroll
-        for (int j = 0; j < kCMax; ++j) {
-          if (in_chunk(j)) {
-            const int x = x0 + j;
-            const double2 f = (EXACT || has_e(x, nL)) ? mp : make_double2(0, 0);
-            zp = cfma(f, zp, z[j]);
-            const double2 ipj = S[slot_of(j)];
-            z[j] = cmul(zp, ipj);
-            mp = cmul(moff, ipj);
-            S[slot_of(j)] = (EXACT || has_e(x + 1, nL)) ? mp : make_double2(0, 0);
-          }
-        }
-        if (XR && last) {
-          // extra row: w = r + (-e / p_{nL-2}) w_{nL-2}, p = d_hi - e^2 / p_{nL-2}
-          const double2 wx = cfma(cmul(moff, ipp_last), zp, xrhs);
-          yx = cmul(wx, crcp_fast(cfms(rc.off2, ipp_last, rc.dhi)));
-        }
-      }
-
-      // ---- 3. back substitution y_x = g_x y_{x+1} + h_x: composition, scan ---
-      Aff B = aff_ident();
 #pragma unroll
       for (int j = kCMax - 1; j >= 0; --j) {
         if (in_chunk(j)) {
-          const double2 gx = S[slot_of(j)];
-          B.f = cmul(gx, B.f);
-          B.g = cfma(gx, B.g, z[j]);
-        }
-      }
-      if (XR && last) {  // the value above the chunk is known: a constant map
-        B.g = cfma(B.f, yx, B.g);
-        B.f = make_double2(0, 0);
-      }
-      const Aff Bin = scan_bwd<P>(B, q, wbuf[1]);
-      {
-        double2 ynext = (XR && last) ? yx : Bin.g;
-#pragma unroll
-        for (int j = kCMax - 1; j >= 0; --j) {
-          if (in_chunk(j)) {
-            ynext = cfma(S[slot_of(j)], ynext, z[j]);
-            z[j] = ynext;
-          }
+          ynext = cfma(S[slot_of(j)], ynext, z[j]);
+          z[j] = ynext;
         }
       }
     }
