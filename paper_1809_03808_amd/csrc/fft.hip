@@ -350,11 +350,13 @@ __global__ __launch_bounds__(threads_of(L), (min_waves_of<L, C, WO>())) void fft
 // epilogue keeps only the scale).  The output kind and the accumulation
 // are template arguments, so that the stores are straight-line code and the
 // compiler's wait for the prefetched values at the top of the loop does not
-// also wait for the previous tile's stores.
-template <int L, typename C, bool OUT128, bool ACC>
+// also wait for the previous tile's stores.  TIN is the input element
+// (complex128 input of a complex64 pass: W = 16 columns, so that the
+// prefetched complex128 values take the registers of 32 complex64 ones).
+template <int L, typename C, typename TIN, int W, bool OUT128, bool ACC>
 __global__ __launch_bounds__(threads_of(L), 1) void fft_stream_kernel(PassDev p0, const void* in, void* out,
                                                                       int64_t ntot) {
-  constexpr int W = tile_w<C>(L);
+  using T = typename RealOf<C>::T;
   constexpr int NT = threads_of(L);
   constexpr int R0 = radix_of(L, 0);
   constexpr int LR = L / R0;
@@ -380,26 +382,26 @@ __global__ __launch_bounds__(threads_of(L), 1) void fft_stream_kernel(PassDev p0
   p.acc = ACC ? 1 : 0;
   p.tw = twl;
   p.scale = scl;
-  C pre[NB * R0];
+  TIN pre[NB * R0];
   // Row r LR + j of a tile: the tile's base (uniform) plus the thread's
-  // 32-bit byte offset (j in_sj + w) sizeof(C) (the launcher checks that
-  // LR in_sj sizeof(C) < 2^31), so that only the thread offsets take
+  // 32-bit byte offset (j in_sj + w) sizeof(TIN) (the launcher checks that
+  // LR in_sj sizeof(TIN) < 2^31), so that only the thread offsets take
   // vector registers besides the values.
   uint32_t toff[NB];
 #pragma unroll
   for (int q = 0; q < NB; ++q)
-    toff[q] = (uint32_t)(((tid + q * NT) / W) * p.in_sj + w) * (uint32_t)sizeof(C);
+    toff[q] = (uint32_t)(((tid + q * NT) / W) * p.in_sj + w) * (uint32_t)sizeof(TIN);
   auto fetch = [&](int64_t tile) -> bool {
     const int64_t o = tile / p.ntile;
     const int64_t i0 = (tile - o * p.ntile) * W;
     const bool ok = i0 + w < p.I;
     const uint32_t msk = ok ? 0xffffffffu : 0u;
-    const char* base = reinterpret_cast<const char*>(reinterpret_cast<const C*>(in) + o * p.in_so + i0);
+    const char* base = reinterpret_cast<const char*>(reinterpret_cast<const TIN*>(in) + o * p.in_so + i0);
 #pragma unroll
     for (int r = 0; r < R0; ++r) {
-      const char* br = base + (int64_t)r * LR * p.in_sj * (int64_t)sizeof(C);
+      const char* br = base + (int64_t)r * LR * p.in_sj * (int64_t)sizeof(TIN);
 #pragma unroll
-      for (int q = 0; q < NB; ++q) pre[q * R0 + r] = *reinterpret_cast<const C*>(br + (toff[q] & msk));
+      for (int q = 0; q < NB; ++q) pre[q * R0 + r] = *reinterpret_cast<const TIN*>(br + (toff[q] & msk));
     }
     return ok;
   };
@@ -410,8 +412,8 @@ __global__ __launch_bounds__(threads_of(L), 1) void fft_stream_kernel(PassDev p0
     C v[NB * R0];
 #pragma unroll
     for (int k = 0; k < NB * R0; ++k) {
-      v[k] = pre[k];
-      if (!ok) v[k].x = v[k].y = 0;
+      v[k].x = ok ? (T)pre[k].x : (T)0;
+      v[k].y = ok ? (T)pre[k].y : (T)0;
     }
     const int64_t o = tile / p.ntile;
     const int64_t i0 = (tile - o * p.ntile) * W;
@@ -524,9 +526,8 @@ int compute_units() {
   return cu[dev];
 }
 
-template <int L, typename C>
+template <int L, typename C, typename TIN, int W>
 hipError_t launch_stream_L(const PassDev& p, int64_t O, const void* in, void* out, hipStream_t s) {
-  constexpr int W = tile_w<C>(L);
   PassDev q = p;
   q.ntile = (p.I + W - 1) / W;
   const int64_t ntot = O * q.ntile;
@@ -534,10 +535,16 @@ hipError_t launch_stream_L(const PassDev& p, int64_t O, const void* in, void* ou
   const int64_t blocks = std::min<int64_t>(ntot, compute_units());
   const dim3 g((unsigned)blocks), b(threads_of(L));
   const bool o128 = p.out_kind == ST_C128;
-  if (o128 && p.acc) hipLaunchKernelGGL((fft_stream_kernel<L, C, true, true>), g, b, 0, s, q, in, out, ntot);
-  else if (o128) hipLaunchKernelGGL((fft_stream_kernel<L, C, true, false>), g, b, 0, s, q, in, out, ntot);
-  else if (p.acc) hipLaunchKernelGGL((fft_stream_kernel<L, C, false, true>), g, b, 0, s, q, in, out, ntot);
-  else hipLaunchKernelGGL((fft_stream_kernel<L, C, false, false>), g, b, 0, s, q, in, out, ntot);
+  if constexpr (sizeof(TIN) != sizeof(C)) {
+    // complex128 input of a complex64 pass: complex64 output, no accumulation
+    if (o128 || p.acc) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((fft_stream_kernel<L, C, TIN, W, false, false>), g, b, 0, s, q, in, out, ntot);
+  } else {
+    if (o128 && p.acc) hipLaunchKernelGGL((fft_stream_kernel<L, C, TIN, W, true, true>), g, b, 0, s, q, in, out, ntot);
+    else if (o128) hipLaunchKernelGGL((fft_stream_kernel<L, C, TIN, W, true, false>), g, b, 0, s, q, in, out, ntot);
+    else if (p.acc) hipLaunchKernelGGL((fft_stream_kernel<L, C, TIN, W, false, true>), g, b, 0, s, q, in, out, ntot);
+    else hipLaunchKernelGGL((fft_stream_kernel<L, C, TIN, W, false, false>), g, b, 0, s, q, in, out, ntot);
+  }
   return hipGetLastError();
 }
 
@@ -548,10 +555,15 @@ template <typename C>
 hipError_t launch_typed(int L, const PassDev& p, int64_t O, const void* in, void* out, hipStream_t s,
                         int small_tile) {
   constexpr int kind = sizeof(C) == sizeof(float2) ? ST_C64 : ST_C128;
-  if (L == 512 && small_tile == 2 && !p.cin && !p.cout && !p.cmode && !p.tw4 && !p.conj_out && p.od == 1 &&
-      p.in_kind == kind &&
-      (int64_t)(L / radix_of(L, 0)) * p.in_sj * (int64_t)sizeof(C) < 0x7fffffffLL)
-    return launch_stream_L<512, C>(p, O, in, out, s);
+  if (L == 512 && small_tile == 2 && !p.cin && !p.cout && !p.cmode && !p.tw4 && !p.conj_out && p.od == 1) {
+    constexpr int64_t LR = 512 / radix_of(512, 0);
+    if (p.in_kind == kind && LR * p.in_sj * (int64_t)sizeof(C) < 0x7fffffffLL)
+      return launch_stream_L<512, C, C, tile_w<C>(512)>(p, O, in, out, s);
+    if constexpr (sizeof(C) == sizeof(float2)) {
+      if (p.in_kind == ST_C128 && p.out_kind == ST_C64 && !p.acc && LR * p.in_sj * (int64_t)sizeof(double2) < 0x7fffffffLL)
+        return launch_stream_L<512, C, double2, 16>(p, O, in, out, s);
+    }
+  }
   if constexpr (sizeof(C) == sizeof(float2)) {
     if (L == 512 && small_tile == 1) return launch_L<512, C, 16>(p, O, in, out, s);
   }
