@@ -255,7 +255,7 @@ __global__ __launch_bounds__(kResThreads) void residual2d_kernel(ResidArgs a, in
 }
 
 // 3D: a block of 8 waves owns an (x_2, x_3) tile of 8 rows x 64 columns and
-// streams along x_1 over a strip of kStrip planes.  For every plane it loads
+// streams along x_1 over a strip of planes.  For every plane it loads
 // the 10 rows the tile needs (one halo row each side; lanes on consecutive
 // x_3), applies the x_3 operators M_3, K_3 (neighbours from adjacent lanes)
 // and parks them in LDS; each thread then forms the plane operators
@@ -270,7 +270,7 @@ constexpr int k3Load = k3Rows + 2;
 
 template <typename TR>
 __global__ __launch_bounds__(k3Threads) void residual3d_kernel(ResidArgs a, int64_t xtiles, int64_t ytiles,
-                                                               int64_t blocks_per_rhs) {
+                                                               int64_t blocks_per_rhs, int strip) {
   __shared__ double2 Mx[2][k3Load][64];
   __shared__ double2 Kx[2][k3Load][64];
   __shared__ double red[2][k3Threads];
@@ -293,7 +293,7 @@ __global__ __launch_bounds__(k3Threads) void residual3d_kernel(ResidArgs a, int6
   const int y0 = (int)yi * k3Rows;      // first output row (x_2) of the tile
   const int y = y0 + wv;                // this wave's output row
   const bool yok = y < n2;
-  const int r0 = (int)si * kStrip, r1 = min(n1, r0 + kStrip);
+  const int r0 = (int)si * strip, r1 = min(n1, r0 + strip);
   const int64_t plane = (int64_t)n2 * n3;
   const int64_t off = b * (int64_t)n1 * plane;
   const double2* U = a.u + off;
@@ -453,11 +453,15 @@ void geometry2d(const int64_t* n, int64_t* xtiles, int64_t* bpr) {
   *bpr = *xtiles * ((n[0] + kStrip - 1) / kStrip);
 }
 
-// 3D streaming geometry: 64-column x 8-row tiles, strips of kStrip planes.
-void geometry3d(const int64_t* n, int64_t* xtiles, int64_t* ytiles, int64_t* bpr) {
+// 3D streaming geometry: 64-column x 8-row tiles, strips of 64 planes when
+// that leaves at least 4096 blocks (16 per compute unit), else of 32: a
+// strip re-reads two halo planes (512^3 x 16 residual: 18.6 ms with strips of
+// 32 planes, 18.1 with 64, 19.7 with 16).
+void geometry3d(const int64_t* n, int nb, int64_t* xtiles, int64_t* ytiles, int64_t* bpr, int* strip) {
   *xtiles = (n[2] + 63) / 64;
   *ytiles = (n[1] + k3Rows - 1) / k3Rows;
-  *bpr = *xtiles * *ytiles * ((n[0] + kStrip - 1) / kStrip);
+  *strip = *xtiles * *ytiles * ((n[0] + 63) / 64) * nb >= 4096 ? 64 : kStrip;
+  *bpr = *xtiles * *ytiles * ((n[0] + *strip - 1) / *strip);
 }
 
 int64_t residual_scratch_len(int dim, const int64_t* grid, int nb) {
@@ -469,7 +473,8 @@ int64_t residual_scratch_len(int dim, const int64_t* grid, int nb) {
     bpr = std::max(bpr, b2);
   } else {
     int64_t xt, yt, b3;
-    geometry3d(grid, &xt, &yt, &b3);
+    int strip;
+    geometry3d(grid, nb, &xt, &yt, &b3, &strip);
     bpr = std::max(bpr, b3);
   }
   return 2 * bpr * nb;
@@ -496,13 +501,16 @@ hipError_t launch_residual(const ResidArgs& a, hipStream_t s) {
   }
   {
     int64_t xt, yt;
-    geometry3d(n, &xt, &yt, &bpr);
+    int strip;
+    geometry3d(n, a.nb, &xt, &yt, &bpr, &strip);
     const int64_t blocks = bpr * a.nb;
     if (blocks > 0x7fffffffLL || 2 * blocks > a.scratch_len) return hipErrorInvalidValue;
     if (a.r_kind == ST_C64)
-      hipLaunchKernelGGL(residual3d_kernel<float2>, dim3((unsigned)blocks), dim3(k3Threads), 0, s, a, xt, yt, bpr);
+      hipLaunchKernelGGL(residual3d_kernel<float2>, dim3((unsigned)blocks), dim3(k3Threads), 0, s, a, xt, yt, bpr,
+                         strip);
     else
-      hipLaunchKernelGGL(residual3d_kernel<double2>, dim3((unsigned)blocks), dim3(k3Threads), 0, s, a, xt, yt, bpr);
+      hipLaunchKernelGGL(residual3d_kernel<double2>, dim3((unsigned)blocks), dim3(k3Threads), 0, s, a, xt, yt, bpr,
+                         strip);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(norm_finish_kernel, dim3((unsigned)a.nb), dim3(kFinThreads), 0, s, a.scratch, bpr, a.norms,
