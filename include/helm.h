@@ -156,7 +156,11 @@ typedef struct helm_plan helm_plan;
  * Errors: HELM_EINVAL, HELM_ESINGULAR (omega = 0: every absorbing face then
  * degenerates to a Neumann face and A annihilates the constants, so it is
  * rejected whatever the mask), HELM_EUNSUPPORTED (no absorbing face on the
- * last axis, or a length beyond the limits above), HELM_ENOMEM, HELM_EDEVICE.
+ * last axis, or a length beyond the limits above), HELM_ENOCONV (the
+ * eigen-setup of an axis found two coinciding eigenvalues: with both faces
+ * absorbing and at most about 3 points per wavelength on that axis, the two
+ * faces' boundary modes share one eigenvalue to rounding, and the plan does
+ * not choose a basis of that eigenspace), HELM_ENOMEM, HELM_EDEVICE.
  */
 int helm_setup(int dim, const int64_t* grid, const double* h, double omega,
                uint32_t abc, const helm_options* opt, helm_plan** out);
@@ -336,7 +340,9 @@ const char* helm_strerror(int code);
  *   vb      host, 4n doubles: boundary rows [2][n] complex: vb[0][l] = v_l(0),
  *           vb[1][l] = v_l(n-1); the common sign of a column is arbitrary
  * Runs no device code.  Errors: HELM_EINVAL, HELM_ENOCONV (root finder or
- * refinement failed), HELM_ENOMEM.
+ * refinement failed, or two eigenvalues coincide to 1e-9 relative, as the
+ * two boundary modes of a doubly absorbing axis do at about 3 points per
+ * wavelength and below), HELM_ENOMEM.
  */
 int helm_eig1d(int64_t n, double h, double omega, int abc_lo, int abc_hi,
                double* lam, double* vb);

@@ -51,3 +51,27 @@ def test_eig1d_large_identities(n, ppw):
     d = np.abs(lam[:, None] - lam[None, :]) + np.eye(n) * 1e300
     assert d.min() > 1.0
     assert np.all(np.isfinite(vb))
+
+
+@pytest.mark.parametrize("ppw, ok", [(4.0, True), (3.0, False), (2.0, False)])
+def test_eig1d_coinciding_boundary_modes(ppw, ok):
+    """Under-resolved axes: at about 3 points per wavelength and below, the
+    boundary modes of the two absorbing faces of n = 63 nodes share one
+    eigenvalue (QZ on the dense pencil: two eigenvalues within 1e-8 relative,
+    with independent eigenvectors), and the eigen-setup reports HELM_ENOCONV
+    instead of returning an arbitrary basis; at 4 points per wavelength the
+    spectrum is simple and the pairs match QZ."""
+    n, h = 63, 1.0 / 62
+    omega = 2 * np.pi / (ppw * h)
+    lam_qz, _ = eigen.abc_pencil(n, h, omega)
+    gap = np.abs(lam_qz[:, None] - lam_qz[None, :]) + np.eye(n) * 1e300
+    coincide = gap.min() < 1e-8 * np.abs(lam_qz).max()
+    assert coincide == (not ok)
+    if ok:
+        lam, _ = helm.eig1d(n, h, omega)
+        order = np.lexsort((lam.imag, lam.real))
+        assert np.max(np.abs(lam[order] - lam_qz)) <= 1e-9 * np.abs(lam_qz).max()
+    else:
+        with pytest.raises(helm.HelmError) as e:
+            helm.eig1d(n, h, omega)
+        assert e.value.code == helm.HELM_ENOCONV

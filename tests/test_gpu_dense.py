@@ -238,3 +238,32 @@ def test_chirp_pass_decision_timed_cached_and_correct(grid, prec, tmp_path):
         else:
             assert np.max(fem.rel_residual(grid, h, omega, abc, u, f.reshape(2, -1))) <= 1e-10
             assert np.max(fem.rel_error(u, ref)) <= 1e-8
+
+
+@pytest.mark.parametrize("prec", [helm.PREC_MIXED, helm.PREC_FP64])
+def test_streaming_pass_walks_several_tiles_per_block(prec, tmp_path):
+    """The streaming 512-point pass (forced through the cache) on a volume
+    whose passes have more tiles than the device has compute units, with a
+    ragged last column tile (63 x 73 = 4599 columns: 144 tiles of 32, the
+    last of 23; 288 tiles of 16 for the complex128-input pass), so that every
+    block walks several tiles: the solution meets the oracle's residual, and
+    the plain FP64 solve needs no refinement."""
+    grid = (512, 63, 73)
+    omega = 2 * np.pi * 6  # at least 10 points per wavelength on every axis
+    h = inputs.spacing(grid)
+    abc = ((True, True),) * 3
+    f = inputs.gaussian_batch(grid, [93, 94])
+    key = f"dim=3 grid={grid[0]}x{grid[1]}x{grid[2]} prec={prec}"
+    forced = tmp_path / "tune.txt"
+    forced.write_text(f"helm-tune {key} fft512=2\n")
+    with helm.Plan(grid, h, omega, precision=prec, check=True, tune_cache=str(forced)) as plan:
+        fd = torch.from_numpy(f).cuda()
+        ud = torch.empty_like(fd)
+        plan.solve(fd, ud)
+        rep = plan.report()
+        u = ud.cpu().numpy().reshape(2, -1)
+    res = fem.rel_residual(grid, h, omega, abc, u, f.reshape(2, -1))
+    _say("  streaming pass", prec, rep, res)
+    assert rep["status"] == 0 and np.max(res) <= 1e-10
+    if prec == helm.PREC_FP64:
+        assert rep["iterations"] == 0
