@@ -110,7 +110,8 @@ __global__ __launch_bounds__(NT) void inner_mid_kernel(InnerMidArgs a) {
       r = cfma(A[k][kp], Mv[kp], r);
       r = cadd(r, cscale(Kv[kp], a.d.dM[k][kp]));
     }
-    a.out[g * per + k * nL + x] = r;
+    if (a.out_c64) reinterpret_cast<float2*>(a.out)[g * per + k * nL + x] = make_float2((float)r.x, (float)r.y);
+    else a.out[g * per + k * nL + x] = r;
   }
 }
 

@@ -153,12 +153,15 @@ struct LineArgs {
   double2 kLo = {1, 0}, kHi = {1, 0};
   const void* in = nullptr;
   int in_kind = ST_C128;
+  // Rank-2 rows PO [nb][2][nI][nL] and PI [nb][nO][2][nL], in the storage
+  // type of the launch's lines (complex64 when in, or else out, is
+  // complex64; complex128 otherwise)
   const double2* alpha0 = nullptr;
   const double2* alpha1 = nullptr;
-  const double2* PO = nullptr;
+  const void* PO = nullptr;
   const double2* beta0 = nullptr;
   const double2* beta1 = nullptr;
-  const double2* PI = nullptr;
+  const void* PI = nullptr;
   void* out = nullptr;
   int out_kind = ST_C128;
   int red = 0;
@@ -256,6 +259,7 @@ struct InnerMidArgs {
   const double2* vb_in;  // nullable
   double2* vb_out;       // nullable
   double2* out;
+  int out_c64 = 0;       // store out in complex64 (the rank-2 rows of complex64 line launches)
   const double2* sO;
   double2 sC;
   BDiff d;

@@ -262,7 +262,8 @@ struct LineDev {
   double hL, m_end, m_int, m_off, k_off;
   double2 kLo, kHi;
   const void* in;
-  const double2 *alpha0, *alpha1, *PO, *beta0, *beta1, *PI, *rho0, *rho1;
+  const double2 *alpha0, *alpha1, *beta0, *beta1, *rho0, *rho1;
+  const void *PO, *PI;  // rank-2 rows, of the lines' storage type
   const double2* piv;   // [nO*nI][P]: reciprocal pivot entering the chunk of each lane
   const double2* sTab;  // [nO*nI] sigma per line, or null
   void* out;
@@ -493,8 +494,8 @@ __global__ __launch_bounds__(NT) void lines_kernel(LineDev a) {
       double2 al0 = make_double2(0, 0), al1 = al0, be0 = al0, be1 = al0;
       if (a.PO) { al0 = a.alpha0[sl]; al1 = a.alpha1[sl]; }
       if (a.PI) { be0 = a.beta0[sm]; be1 = a.beta1[sm]; }
-      const double2* po = a.PO ? a.PO + (int64_t)(sb * 2) * a.nI * nL + (int64_t)sm * nL : nullptr;
-      const double2* pi = a.PI ? a.PI + (int64_t)((sb * a.nO + sl) * 2) * nL : nullptr;
+      const T* po = a.PO ? reinterpret_cast<const T*>(a.PO) + (int64_t)(sb * 2) * a.nI * nL + (int64_t)sm * nL : nullptr;
+      const T* pi = a.PI ? reinterpret_cast<const T*>(a.PI) + (int64_t)((sb * a.nO + sl) * 2) * nL : nullptr;
       // one source at a time (each lane revisits only its own staging slots),
       // so that at most kCMax loads are in flight per lane
       if (a.in && PREF) {
@@ -566,7 +567,7 @@ __global__ __launch_bounds__(NT) void lines_kernel(LineDev a) {
       if constexpr (NBAT > 0) {
 #pragma unroll
         for (int src = 0; src < 2; ++src) {
-          const double2* rows = src == 0 ? po : pi;
+          const T* rows = src == 0 ? po : pi;
           if (!rows) continue;
           const int64_t stride = src == 0 ? (int64_t)a.nI * nL : (int64_t)nL;
           const double2 w0 = src == 0 ? al0 : be0, w1 = src == 0 ? al1 : be1;
@@ -577,8 +578,8 @@ __global__ __launch_bounds__(NT) void lines_kernel(LineDev a) {
             for (int u = 0; u < NBAT; ++u) {
               const int r = (j0 + u) * 64 + lane, x = wx0 + r;
               const bool ok = r < seg && x < nL && sv;
-              p0[u] = ok ? rows[x] : make_double2(0, 0);
-              p1[u] = ok ? rows[stride + x] : make_double2(0, 0);
+              p0[u] = ok ? to_d2(rows[x]) : make_double2(0, 0);
+              p1[u] = ok ? to_d2(rows[stride + x]) : make_double2(0, 0);
             }
 #pragma unroll
             for (int u = 0; u < NBAT; ++u) {
@@ -599,8 +600,8 @@ __global__ __launch_bounds__(NT) void lines_kernel(LineDev a) {
             const int r = jj * 64 + lane, x = wx0 + r;
             if (r < seg && x < nL && sv) {
               double2 d = S[stage_pos(si * seg + r)];
-              d = cfma(al0, po[x], d);
-              d = cfma(al1, po[(int64_t)a.nI * nL + x], d);
+              d = cfma(al0, to_d2(po[x]), d);
+              d = cfma(al1, to_d2(po[(int64_t)a.nI * nL + x]), d);
               S[stage_pos(si * seg + r)] = d;
             }
           }
@@ -611,8 +612,8 @@ __global__ __launch_bounds__(NT) void lines_kernel(LineDev a) {
             const int r = jj * 64 + lane, x = wx0 + r;
             if (r < seg && x < nL && sv) {
               double2 d = S[stage_pos(si * seg + r)];
-              d = cfma(be0, pi[x], d);
-              d = cfma(be1, pi[nL + x], d);
+              d = cfma(be0, to_d2(pi[x]), d);
+              d = cfma(be1, to_d2(pi[nL + x]), d);
               S[stage_pos(si * seg + r)] = d;
             }
           }
@@ -639,14 +640,14 @@ __global__ __launch_bounds__(NT) void lines_kernel(LineDev a) {
       if (a.in) xrhs = to_d2(reinterpret_cast<const T*>(a.in)[loff + x]);
       else if (a.unit_rhs && (int)b == x) xrhs = make_double2(1, 0);
       if (a.PO) {
-        const double2* po = a.PO + (int64_t)(b * 2) * a.nI * nL + (int64_t)m * nL;
-        xrhs = cfma(a.alpha0[l], po[x], xrhs);
-        xrhs = cfma(a.alpha1[l], po[(int64_t)a.nI * nL + x], xrhs);
+        const T* po = reinterpret_cast<const T*>(a.PO) + (int64_t)(b * 2) * a.nI * nL + (int64_t)m * nL;
+        xrhs = cfma(a.alpha0[l], to_d2(po[x]), xrhs);
+        xrhs = cfma(a.alpha1[l], to_d2(po[(int64_t)a.nI * nL + x]), xrhs);
       }
       if (a.PI) {
-        const double2* pi = a.PI + (int64_t)((b * a.nO + l) * 2) * nL;
-        xrhs = cfma(a.beta0[m], pi[x], xrhs);
-        xrhs = cfma(a.beta1[m], pi[nL + x], xrhs);
+        const T* pi = reinterpret_cast<const T*>(a.PI) + (int64_t)((b * a.nO + l) * 2) * nL;
+        xrhs = cfma(a.beta0[m], to_d2(pi[x]), xrhs);
+        xrhs = cfma(a.beta1[m], to_d2(pi[nL + x]), xrhs);
       }
     }
 

@@ -818,7 +818,7 @@ struct InnerIO {
   const double2* sO = nullptr;
   const void* in = nullptr;
   int in_kind = ST_C128;
-  const double2* PO = nullptr;
+  const void* PO = nullptr;  // rank-2 rows, in the storage type of the lines
   const double2* alpha0 = nullptr;
   const double2* alpha1 = nullptr;
   void* out = nullptr;
@@ -928,7 +928,7 @@ int inner_solve(helm_plan* p, const Level& lv, const InnerIO& io, hipStream_t st
     s2.sI = I.sigA;
     s2.piv = io.seedA;
     s2.sTab = io.sigTA;
-    s2.PI = p->PIb.as<double2>();
+    s2.PI = p->PIb.p;  // complex128: the launch has no line storage
     s2.beta0 = I.va0d;
     s2.beta1 = I.va1d;
     s2.red = 1;
@@ -940,8 +940,11 @@ int inner_solve(helm_plan* p, const Level& lv, const InnerIO& io, hipStream_t st
     HCHK(timed(p, K_LINES, 0.0, st, [&] { return launch_lines(s2, st); }));
   }
 
+  // the Step-3 launch reads these rows (PI) in its lines' storage type
+  const int k3 = io.in ? io.in_kind : (io.out ? io.out_kind : ST_C128);
   m.vb_in = p->VB.as<double2>();
   m.vb_out = nullptr;
+  m.out_c64 = k3 == ST_C64;
   HCHK(timed(p, K_INNER_MID, (double)lv.nb * lv.nO * 2 * lv.nL * sizeof(double2) * (m.ntiles + 2), st,
              [&] { return launch_inner_mid(m, st); }));
 
@@ -953,7 +956,7 @@ int inner_solve(helm_plan* p, const Level& lv, const InnerIO& io, hipStream_t st
   s3.PO = io.PO;
   s3.alpha0 = io.alpha0;
   s3.alpha1 = io.alpha1;
-  s3.PI = p->PIb.as<double2>();
+  s3.PI = p->PIb.p;
   s3.beta0 = I.genB0;
   s3.beta1 = I.genB1;
   if (io.rhoL0) {
@@ -1217,13 +1220,13 @@ int solve_once(helm_plan* p, const void* x, int x_kind, double2* u, int accumula
                    Rh, ST_C128, st);
       if (rc) return rc;
     }
-    // q = C_1 (v_b + w_b), transformed along x_2 and scaled by 1/mu_2
+    // q = C_1 (v_b + w_b), transformed along x_2 and scaled by 1/mu_2; stored
+    // in the lines' storage type, as the rank-2 rows of the Step-3 lines
     om.a = Vp;
     om.c = Wp;
     om.r = Vh;
     HCHK(timed(p, K_OUTER_MID, (double)nb * 2 * plane * sizeof(double2) * 3, st, [&] { return launch_outer_mid(om, st); }));
-    rc = run_fft(p, A2, -1, false, Vh, ST_C128, Rh, ST_C128, (int64_t)nb * 2, n3, A2.invmu, 1.0, 0, Wp,
-                 ST_C128, st);
+    rc = run_fft(p, A2, -1, false, Vh, ST_C128, Rh, T, (int64_t)nb * 2, n3, A2.invmu, 1.0, 0, Wp, ST_C128, st);
     if (rc) return rc;
   }
   // Outer step 3: corrected periodic solve, stored, then inverse transforms.
@@ -1986,7 +1989,7 @@ int measure_boundary(helm_plan* p, int nb, double* t_lines, double* t_tab) {
   s2.kHi = p->kHi;
   s2.sTab = p->sig[1];
   s2.piv = p->seed[1];
-  s2.PI = pi.as<double2>();
+  s2.PI = pi.p;
   s2.beta0 = A2.va0d;
   s2.beta1 = A2.va1d;
   s2.red = 1;
@@ -2081,7 +2084,7 @@ int tune_layout(helm_plan* p) {
   la.piv = p->seed[0];
   la.in = in.p;
   la.in_kind = fp32 ? ST_C64 : ST_C128;
-  la.PI = pi.as<double2>();
+  la.PI = pi.p;  // in the storage type of the lines (filled with finite bytes either way)
   la.beta0 = A2.genB0;
   la.beta1 = A2.genB1;
   la.rho0 = A1.redB0;
