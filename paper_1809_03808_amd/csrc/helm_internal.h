@@ -154,14 +154,15 @@ struct LineArgs {
   const void* in = nullptr;
   int in_kind = ST_C128;
   // Rank-2 rows PO [nb][2][nI][nL] and PI [nb][nO][2][nL], in the storage
-  // type of the launch's lines (complex64 when in, or else out, is
-  // complex64; complex128 otherwise)
+  // type of the launch's lines (that of in, or else of out; complex128 with
+  // neither); r2_kind states their type and must match (checked)
   const double2* alpha0 = nullptr;
   const double2* alpha1 = nullptr;
   const void* PO = nullptr;
   const double2* beta0 = nullptr;
   const double2* beta1 = nullptr;
   const void* PI = nullptr;
+  int r2_kind = ST_C128;
   void* out = nullptr;
   int out_kind = ST_C128;
   int red = 0;

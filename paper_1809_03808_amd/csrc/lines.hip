@@ -1026,9 +1026,10 @@ hipError_t launch_lines(LineArgs a, hipStream_t s) {
   }
   if (blocks <= 0) return hipSuccess;
   if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
-  // one storage kind for the input and output lines
+  // one storage kind for the input and output lines and the rank-2 rows
   if ((a.in && a.out && a.in_kind != a.out_kind)) return hipErrorInvalidValue;
   const int kind = a.in ? a.in_kind : a.out_kind;
+  if ((a.PO || a.PI) && a.r2_kind != kind) return hipErrorInvalidValue;
   return kind == ST_C64 ? launch_typed<float2>(d, P, blocks, s) : launch_typed<double2>(d, P, blocks, s);
 }
 

@@ -819,6 +819,7 @@ struct InnerIO {
   const void* in = nullptr;
   int in_kind = ST_C128;
   const void* PO = nullptr;  // rank-2 rows, in the storage type of the lines
+  int PO_kind = ST_C128;
   const double2* alpha0 = nullptr;
   const double2* alpha1 = nullptr;
   void* out = nullptr;
@@ -886,6 +887,7 @@ int inner_solve(helm_plan* p, const Level& lv, const InnerIO& io, hipStream_t st
   s1.in = io.in;
   s1.in_kind = io.in_kind;
   s1.PO = io.PO;
+  s1.r2_kind = io.PO_kind;
   s1.alpha0 = io.alpha0;
   s1.alpha1 = io.alpha1;
   s1.red = 1;
@@ -929,6 +931,7 @@ int inner_solve(helm_plan* p, const Level& lv, const InnerIO& io, hipStream_t st
     s2.piv = io.seedA;
     s2.sTab = io.sigTA;
     s2.PI = p->PIb.p;  // complex128: the launch has no line storage
+    s2.r2_kind = ST_C128;
     s2.beta0 = I.va0d;
     s2.beta1 = I.va1d;
     s2.red = 1;
@@ -954,6 +957,8 @@ int inner_solve(helm_plan* p, const Level& lv, const InnerIO& io, hipStream_t st
   s3.in = io.in;
   s3.in_kind = io.in_kind;
   s3.PO = io.PO;
+  s3.r2_kind = k3;  // PIb as stored above; PO was stored the same way
+  if (io.PO && io.PO_kind != k3) return HELM_EINVAL;
   s3.alpha0 = io.alpha0;
   s3.alpha1 = io.alpha1;
   s3.PI = p->PIb.p;
@@ -1241,6 +1246,7 @@ int solve_once(helm_plan* p, const void* x, int x_kind, double2* u, int accumula
     io.in = W0;
     io.in_kind = T;
     io.PO = Rh;
+    io.PO_kind = T;
     io.alpha0 = A1.genB0;
     io.alpha1 = A1.genB1;
     io.out = W0;
@@ -1990,6 +1996,7 @@ int measure_boundary(helm_plan* p, int nb, double* t_lines, double* t_tab) {
   s2.sTab = p->sig[1];
   s2.piv = p->seed[1];
   s2.PI = pi.p;
+  s2.r2_kind = ST_C128;
   s2.beta0 = A2.va0d;
   s2.beta1 = A2.va1d;
   s2.red = 1;
@@ -2085,6 +2092,7 @@ int tune_layout(helm_plan* p) {
   la.in = in.p;
   la.in_kind = fp32 ? ST_C64 : ST_C128;
   la.PI = pi.p;  // in the storage type of the lines (filled with finite bytes either way)
+  la.r2_kind = la.in_kind;
   la.beta0 = A2.genB0;
   la.beta1 = A2.genB1;
   la.rho0 = A1.redB0;
