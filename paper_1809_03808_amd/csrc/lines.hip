@@ -392,8 +392,12 @@ __device__ inline int stage_pos(int e) { return e + (e >> 3); }
 // (its pivot and value follow from the chunk's last ones), takes y_{nL-1},
 // and folds it into its backward map, which becomes the constant map to the
 // value entering its chunk from above.
+// Storing launches of exact 512-lane lines (4096-row lines) are held to 128
+// registers, so that two blocks of eight waves share a compute unit (the
+// complex64 kernel needs 131 otherwise and then spills 2; 4096^2 mixed
+// solve: line launches 0.365 -> 0.344 ms).
 template <typename T, int NT, int P, int C, bool RED, bool XR, bool PAD>
-__global__ __launch_bounds__(NT) void lines_kernel(LineDev a) {
+__global__ __launch_bounds__(NT, (!RED && NT == 512 && !XR && !PAD) ? 4 : 1) void lines_kernel(LineDev a) {
   constexpr int NW = NT / 64;
   constexpr int PW = P < 64 ? P : 64;     // lanes of one line inside a wave
   constexpr int SPW = 64 / PW;            // lines per wave
