@@ -2135,11 +2135,13 @@ int tune_layout(helm_plan* p) {
   return HELM_OK;
 }
 
-// Tile of the complex64 512-point transform passes (mixed-precision plans
-// with such a pass along a power-of-two axis): the 128 KB tile (32 columns,
-// one block per compute unit) or the 64 KB one (16 columns, two blocks),
-// each timed on the forward transform along the first such axis over a
-// volume of the plan's shape; cached as "fft512=".
+// Form of the 512-point transform passes (plans with such a pass along a
+// power-of-two axis): the 128 KB tile with one block per tile, the 64 KB
+// complex64 tile (two blocks per compute unit; mixed-precision plans only),
+// or the streaming pass (one persistent block per compute unit, the next
+// tile's loads in flight), each timed on the forward transform along the
+// first such axis over a volume of the plan's shape and precision; cached as
+// "fft512=".
 int tune_fft_tile(helm_plan* p) {
   const bool fp32 = p->opt.precision == HELM_PREC_MIXED;
   int axis = -1;
