@@ -197,6 +197,16 @@ def test_fft_tile_decision_timed_cached_and_correct(grid, prec, tmp_path):
             assert np.max(res) <= 1e-10 and np.max(err) <= 1e-8
         else:
             assert rep["iterations"] == 0 and np.max(err) <= 1e-9
+    if not mixed:
+        # the 64 KB complex64 tile is no choice for an FP64 plan: a cached
+        # "fft512=1" is ignored and the forms are timed again
+        forced = tmp_path / "forced_bad.txt"
+        forced.write_text(f"helm-tune {key} fft512=1\n")
+        with helm.Plan(grid, h, omega, precision=prec, tune_cache=str(forced)) as plan:
+            pass
+        lines = [ln for ln in forced.read_text().splitlines() if "fft512=" in ln]
+        picked = [t for t in lines[-1].split() if t.startswith("fft512=")]
+        assert len(lines) == 2 and picked in (["fft512=0"], ["fft512=2"]), lines
 
 
 @pytest.mark.parametrize("grid,prec", [
