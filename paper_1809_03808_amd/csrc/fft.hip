@@ -12,6 +12,7 @@
 // exactly once each way.  Long axes are split into two passes (four-step:
 // n = n_a n_b, twiddle e^{-2 pi i a c/n} between the passes).
 #include <algorithm>
+#include <atomic>
 
 #include "helm_internal.h"
 
@@ -514,16 +515,18 @@ hipError_t launch_L(const PassDev& p, int64_t O, const void* in, void* out, hipS
 }
 
 // Compute units of the current device, for the streaming pass's grid.
+// (Cached per device; threads that race on the first query store the same
+// value.)
 int compute_units() {
-  static int cu[64] = {0};
+  static std::atomic<int> cu[64];
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
-  if (cu[dev] <= 0) {
-    int n = 0;
+  int n = cu[dev].load(std::memory_order_relaxed);
+  if (n <= 0) {
     if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) n = 256;
-    cu[dev] = n;
+    cu[dev].store(n, std::memory_order_relaxed);
   }
-  return cu[dev];
+  return n;
 }
 
 template <int L, typename C, typename TIN, int W>
